@@ -1,0 +1,434 @@
+"""Python binding of the MI355X probe library (libgace.so, C ABI in include/gace.h).
+
+Argument marshalling only: every step of the probe runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and streams.  There is no
+fallback: if libgace.so is missing, importing the binding's functions raises.
+
+Names follow the C ABI: gace_create, gace_probe_selectivity, gace_join_freq,
+gace_batch_run, gace_autotune, gace_server_create / submit / wait / destroy ...
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgace.so")
+
+GACE_OK, GACE_EINVAL, GACE_ENOMEM, GACE_EOVERFLOW, GACE_EDEVICE, GACE_EBUSY, GACE_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EOVERFLOW", -4: "EDEVICE", -5: "EBUSY", -6: "ETIMEOUT"}
+I32, I64, F32 = 1, 2, 3
+RANGE, EQ, IN = 1, 2, 3
+REQ_SELECTIVITY, REQ_JOIN = 1, 2
+
+
+class GaceError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+# ---------------------------------------------------------------- C structs
+class gace_column(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class gace_table(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_uint64), ("cols", ctypes.POINTER(gace_column)),
+                ("n_cols", ctypes.c_uint32), ("table_id", ctypes.c_uint32)]
+
+
+class gace_term(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_uint32), ("op", ctypes.c_uint32), ("n_vals", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("v", ctypes.c_int64 * 8)]
+
+
+class gace_predicates(ctypes.Structure):
+    _fields_ = [("terms", ctypes.POINTER(gace_term)), ("pred_off", ctypes.POINTER(ctypes.c_uint32)),
+                ("n_preds", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class gace_sample_spec(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("rate", ctypes.c_double), ("block_rows", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class gace_probe_info(ctypes.Structure):
+    _fields_ = [("sampled_rows", ctypes.c_uint64), ("kept_blocks", ctypes.c_uint64)]
+
+
+class gace_keys(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("n", ctypes.c_uint64), ("table_id", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("spec", gace_sample_spec)]
+
+
+class gace_join_result(ctypes.Structure):
+    _fields_ = [("join_card", ctypes.c_uint64), ("ndv_R", ctypes.c_uint64), ("ndv_S", ctypes.c_uint64),
+                ("n_R", ctypes.c_uint64), ("n_S", ctypes.c_uint64)]
+
+
+class gace_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("table", gace_table), ("preds", gace_predicates), ("spec", gace_sample_spec),
+                ("counts", ctypes.POINTER(ctypes.c_uint64)), ("info", ctypes.POINTER(gace_probe_info)),
+                ("R", gace_keys), ("S", gace_keys), ("join", ctypes.POINTER(gace_join_result))]
+
+
+class gace_schedule(ctypes.Structure):
+    _fields_ = [("wg_threads", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32), ("item_rows", ctypes.c_uint32),
+                ("count_mode", ctypes.c_uint32), ("join_cache_slots", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 3)]
+
+
+class gace_server_cfg(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("queue_capacity", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("workspace_bytes", ctypes.c_uint64)]
+
+
+class gace_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "batches", "queued",
+                                                "inflight", "workspace_in_use", "workspace_peak")]
+
+
+ABI_FUNCTIONS = [
+    "gace_create", "gace_destroy", "gace_last_error", "gace_version", "gace_check_request",
+    "gace_probe_selectivity", "gace_join_freq", "gace_batch_run", "gace_autotune", "gace_get_schedule",
+    "gace_set_schedule", "gace_last_batch_stats", "gace_server_create", "gace_server_submit",
+    "gace_server_wait", "gace_server_stats_get", "gace_server_destroy",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libgace.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except Exception:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgace.so is not built: run __graft_entry__.build() (or "
+                               "python paper_2512_19750_amd/build.py) first")
+        L = ctypes.CDLL(LIB_PATH)
+        P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+        sig = {
+            "gace_create": ([ctypes.c_int, u64, ctypes.POINTER(P)], i32),
+            "gace_destroy": ([P], i32),
+            "gace_last_error": ([], ctypes.c_char_p),
+            "gace_version": ([], ctypes.c_char_p),
+            "gace_check_request": ([ctypes.POINTER(gace_request)], i32),
+            "gace_probe_selectivity": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
+                                        ctypes.POINTER(gace_sample_spec), ctypes.POINTER(ctypes.c_uint64),
+                                        ctypes.POINTER(gace_probe_info), P], i32),
+            "gace_join_freq": ([P, ctypes.POINTER(gace_keys), ctypes.POINTER(gace_keys),
+                                ctypes.POINTER(gace_join_result), P], i32),
+            "gace_batch_run": ([P, ctypes.POINTER(gace_request), u32, ctypes.POINTER(i32), P], i32),
+            "gace_autotune": ([P, ctypes.POINTER(gace_request), u32, ctypes.c_char_p, P], i32),
+            "gace_get_schedule": ([P, ctypes.POINTER(gace_schedule)], i32),
+            "gace_set_schedule": ([P, ctypes.POINTER(gace_schedule)], i32),
+            "gace_last_batch_stats": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
+                                       ctypes.POINTER(u64)], i32),
+            "gace_server_create": ([ctypes.c_int, ctypes.POINTER(gace_server_cfg), ctypes.POINTER(P)], i32),
+            "gace_server_submit": ([P, ctypes.POINTER(gace_request), ctypes.POINTER(u64)], i32),
+            "gace_server_wait": ([P, u64, ctypes.c_int64, ctypes.POINTER(i32)], i32),
+            "gace_server_stats_get": ([P, ctypes.POINTER(gace_server_stats)], i32),
+            "gace_server_destroy": ([P], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().gace_last_error().decode()
+
+
+def _check(st: int):
+    if st != GACE_OK:
+        raise GaceError(st, last_error())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------- marshalling
+_TORCH_DTYPE = None
+
+
+def _dtype_code(t) -> int:
+    import torch
+    m = {torch.int32: I32, torch.int64: I64, torch.float32: F32}
+    if t.dtype not in m:
+        raise TypeError("column dtype must be int32, int64 or float32")
+    return m[t.dtype]
+
+
+@dataclass
+class Table:
+    """Device-resident column-major table: a list of 1-D tensors of equal length."""
+    cols: list
+    table_id: int
+
+    @property
+    def n_rows(self) -> int:
+        return int(self.cols[0].shape[0]) if self.cols else 0
+
+
+@dataclass
+class Keys:
+    keys: object          # 1-D int64 device tensor
+    table_id: int
+    seed: int = 0
+    rate: float = 1.0
+    block_rows: int = 4096
+
+
+def _f32_bits(x) -> int:
+    return int(np.array([x], dtype=np.float32).view(np.uint32)[0])
+
+
+class _Keep:
+    """Holds the ctypes arrays a request points to."""
+    def __init__(self):
+        self.objs = []
+
+    def add(self, o):
+        self.objs.append(o)
+        return o
+
+
+def _make_table(t: Table, keep: _Keep) -> gace_table:
+    cols = keep.add((gace_column * max(len(t.cols), 1))())
+    for i, c in enumerate(t.cols):
+        cols[i].data = c.data_ptr()
+        cols[i].dtype = _dtype_code(c)
+    g = gace_table()
+    g.n_rows = t.n_rows
+    g.cols = ctypes.cast(cols, ctypes.POINTER(gace_column))
+    g.n_cols = len(t.cols)
+    g.table_id = t.table_id
+    return g
+
+
+def _make_preds(preds, dtypes: Sequence[int], keep: _Keep) -> gace_predicates:
+    n_terms = sum(len(p) for p in preds)
+    terms = keep.add((gace_term * max(n_terms, 1))())
+    off = keep.add((ctypes.c_uint32 * (len(preds) + 1))())
+    k = 0
+    for i, p in enumerate(preds):
+        for (col, op, vals) in p:
+            terms[k].col = col
+            terms[k].op = op
+            terms[k].n_vals = len(vals)
+            dt = dtypes[col] if 0 <= col < len(dtypes) else 0
+            for j, v in enumerate(vals[:8]):      # the library rejects n_vals > 8 itself
+                terms[k].v[j] = _f32_bits(v) if dt == F32 else int(v)
+            k += 1
+        off[i + 1] = k
+    g = gace_predicates()
+    g.terms = ctypes.cast(terms, ctypes.POINTER(gace_term))
+    g.pred_off = ctypes.cast(off, ctypes.POINTER(ctypes.c_uint32))
+    g.n_preds = len(preds)
+    return g
+
+
+def _make_spec(seed: int, rate: float, block_rows: int) -> gace_sample_spec:
+    s = gace_sample_spec()
+    s.seed = seed & (2**64 - 1)
+    s.rate = rate
+    s.block_rows = block_rows
+    return s
+
+
+def _make_keys(k: Keys) -> gace_keys:
+    g = gace_keys()
+    g.keys = k.keys.data_ptr() if k.keys is not None else 0
+    g.n = int(k.keys.shape[0]) if k.keys is not None else 0
+    g.table_id = k.table_id
+    g.spec = _make_spec(k.seed, k.rate, k.block_rows)
+    return g
+
+
+class SelRequest:
+    def __init__(self, table: Table, preds, seed: int = 0, rate: float = 1.0, block_rows: int = 4096):
+        self.table, self.preds, self.seed, self.rate, self.block_rows = table, preds, seed, rate, block_rows
+        self.counts = np.zeros(max(len(preds), 1), dtype=np.uint64)
+        self.info = gace_probe_info()
+        self.status = None
+
+    def fill(self, r: gace_request, keep: _Keep):
+        r.kind = REQ_SELECTIVITY
+        r.table = _make_table(self.table, keep)
+        r.preds = _make_preds(self.preds, [_dtype_code(c) for c in self.table.cols], keep)
+        r.spec = _make_spec(self.seed, self.rate, self.block_rows)
+        r.counts = self.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        r.info = ctypes.pointer(self.info)
+        keep.add(self.counts)
+
+    def result(self):
+        return self.counts[:len(self.preds)].copy(), int(self.info.sampled_rows), int(self.info.kept_blocks)
+
+
+class JoinRequest:
+    def __init__(self, R: Keys, S: Keys):
+        self.R, self.S = R, S
+        self.out = gace_join_result()
+        self.status = None
+
+    def fill(self, r: gace_request, keep: _Keep):
+        r.kind = REQ_JOIN
+        r.R = _make_keys(self.R)
+        r.S = _make_keys(self.S)
+        r.join = ctypes.pointer(self.out)
+
+    def result(self):
+        o = self.out
+        return dict(join_card=int(o.join_card), ndv_R=int(o.ndv_R), ndv_S=int(o.ndv_S),
+                    n_R=int(o.n_R), n_S=int(o.n_S))
+
+
+def make_requests(reqs) -> Tuple[ctypes.Array, _Keep]:
+    keep = _Keep()
+    arr = (gace_request * max(len(reqs), 1))()
+    for i, q in enumerate(reqs):
+        q.fill(arr[i], keep)
+    return arr, keep
+
+
+# ---------------------------------------------------------------- ABI wrappers
+def gace_version() -> str:
+    return lib().gace_version().decode()
+
+
+def gace_create(device: int = 0, workspace_bytes: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().gace_create(device, workspace_bytes, ctypes.byref(h)))
+    return h.value
+
+
+def gace_destroy(ctx: int):
+    _check(lib().gace_destroy(ctx))
+
+
+def gace_check_request(req) -> int:
+    arr, keep = make_requests([req])
+    return int(lib().gace_check_request(arr))
+
+
+def gace_probe_selectivity(ctx: int, table: Table, preds, seed: int = 0, rate: float = 1.0,
+                           block_rows: int = 4096, stream=None):
+    """-> (counts uint64[n_preds], sampled_rows, kept_blocks)"""
+    keep = _Keep()
+    t = _make_table(table, keep)
+    p = _make_preds(preds, [_dtype_code(c) for c in table.cols], keep)
+    s = _make_spec(seed, rate, block_rows)
+    counts = np.zeros(max(len(preds), 1), dtype=np.uint64)
+    info = gace_probe_info()
+    _check(lib().gace_probe_selectivity(ctx, ctypes.byref(t), ctypes.byref(p), ctypes.byref(s),
+                                        counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                        ctypes.byref(info), _stream_handle(stream)))
+    return counts[:len(preds)], int(info.sampled_rows), int(info.kept_blocks)
+
+
+def gace_join_freq(ctx: int, R: Keys, S: Keys, stream=None) -> dict:
+    r, s = _make_keys(R), _make_keys(S)
+    out = gace_join_result()
+    _check(lib().gace_join_freq(ctx, ctypes.byref(r), ctypes.byref(s), ctypes.byref(out), _stream_handle(stream)))
+    return dict(join_card=int(out.join_card), ndv_R=int(out.ndv_R), ndv_S=int(out.ndv_S),
+                n_R=int(out.n_R), n_S=int(out.n_S))
+
+
+def gace_batch_run(ctx: int, reqs, stream=None, raise_on_error: bool = True, prepared=None) -> List[int]:
+    """Runs SelRequest / JoinRequest objects in one batched launch; results land
+    in each object (.result()).  Returns the per-request statuses."""
+    arr, keep = prepared if prepared is not None else make_requests(reqs)
+    per = (ctypes.c_int32 * max(len(reqs), 1))()
+    st = lib().gace_batch_run(ctx, arr, len(reqs), per, _stream_handle(stream))
+    for i, q in enumerate(reqs):
+        q.status = int(per[i])
+    if raise_on_error and st != GACE_OK:
+        raise GaceError(st, last_error())
+    return [int(per[i]) for i in range(len(reqs))]
+
+
+def gace_autotune(ctx: int, reqs, cache_path: Optional[str] = None, stream=None):
+    arr, keep = make_requests(reqs)
+    _check(lib().gace_autotune(ctx, arr, len(reqs), cache_path.encode() if cache_path else None,
+                               _stream_handle(stream)))
+
+
+def gace_get_schedule(ctx: int) -> dict:
+    s = gace_schedule()
+    _check(lib().gace_get_schedule(ctx, ctypes.byref(s)))
+    return dict(wg_threads=s.wg_threads, wgs_per_cu=s.wgs_per_cu, item_rows=s.item_rows,
+                count_mode=s.count_mode, join_cache_slots=s.join_cache_slots)
+
+
+def gace_set_schedule(ctx: int, **kw):
+    s = gace_schedule()
+    _check(lib().gace_get_schedule(ctx, ctypes.byref(s)))
+    for k, v in kw.items():
+        setattr(s, k, v)
+    _check(lib().gace_set_schedule(ctx, ctypes.byref(s)))
+
+
+def gace_last_batch_stats(ctx: int) -> dict:
+    ms = ctypes.c_double()
+    ab = ctypes.c_uint64()
+    rp = ctypes.c_uint64()
+    _check(lib().gace_last_batch_stats(ctx, ctypes.byref(ms), ctypes.byref(ab), ctypes.byref(rp)))
+    return dict(kernel_ms=ms.value, alg_bytes=int(ab.value), rows_preds=int(rp.value))
+
+
+def gace_server_create(device: int = 0, max_inflight: int = 2, max_batch: int = 256,
+                       queue_capacity: int = 4096, workspace_bytes: int = 8 << 30) -> int:
+    cfg = gace_server_cfg()
+    cfg.max_inflight = max_inflight
+    cfg.max_batch = max_batch
+    cfg.queue_capacity = queue_capacity
+    cfg.workspace_bytes = workspace_bytes
+    h = ctypes.c_void_p()
+    _check(lib().gace_server_create(device, ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def gace_server_submit(srv: int, req) -> int:
+    """Submit one SelRequest / JoinRequest; keeps its ctypes arrays alive on the
+    request object until it completes.  Returns the ticket."""
+    arr, keep = make_requests([req])
+    req._keep = (arr, keep)
+    t = ctypes.c_uint64()
+    _check(lib().gace_server_submit(srv, arr, ctypes.byref(t)))
+    return int(t.value)
+
+
+def gace_server_wait(srv: int, ticket: int, timeout_ns: int = -1) -> int:
+    st = ctypes.c_int32()
+    _check(lib().gace_server_wait(srv, ticket, timeout_ns, ctypes.byref(st)))
+    return int(st.value)
+
+
+def gace_server_stats_get(srv: int) -> dict:
+    s = gace_server_stats()
+    _check(lib().gace_server_stats_get(srv, ctypes.byref(s)))
+    return {n: int(getattr(s, n)) for n, _ in gace_server_stats._fields_}
+
+
+def gace_server_destroy(srv: int):
+    _check(lib().gace_server_destroy(srv))

@@ -1,0 +1,675 @@
+// compile.cpp -- request validation and compilation (host only).
+//
+// A conjunctive predicate is turned into per-column programs: on each column
+// the terms' accepted values form intervals on an order-preserving unsigned
+// key line (int32 and float32 map to 32-bit keys, int64 to 64-bit keys).  All
+// interval endpoints of a 64-predicate group on a column cut the key line into
+// elementary intervals on which every term is constant; each elementary
+// interval gets a 64-bit mask with bit p set when predicate p's terms on that
+// column all accept it.  At run time a row's mask is the AND over the
+// referenced columns of mask[interval(value)], so the per-row work is one
+// lookup per column instead of one comparison per term (Sec. III-B "Key-Only
+// + Bitmask": only the referenced columns are read; bits are never stored).
+#include "compile.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+namespace gace {
+
+typedef unsigned __int128 u128;
+
+uint64_t rate_threshold(double rate) {
+    if (rate >= 1.0) return kThrAll;
+    if (!(rate > 0.0)) return 0;
+    return (uint64_t)std::floor(rate * 4294967296.0);
+}
+
+static float f32_of(int64_t v) {
+    uint32_t b = (uint32_t)(uint64_t)v;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+
+static uint32_t f32_key(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u << 1) == 0u) u = 0u;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// ------------------------------------------------------------------ checks
+gace_status check_spec(const gace_sample_spec* s, std::string& msg) {
+    if (!s) return GACE_OK;
+    if (!(s->rate >= 0.0 && s->rate <= 1.0)) {
+        msg = "sample rate must be in [0, 1]";
+        return GACE_EINVAL;
+    }
+    const uint32_t b = s->block_rows;
+    if (b == 0 || b > (1u << 20) || (b & (b - 1))) {
+        msg = "block_rows must be a power of two in [1, 2^20]";
+        return GACE_EINVAL;
+    }
+    return GACE_OK;
+}
+
+gace_status check_selectivity(const gace_table* t, const gace_predicates* p, const gace_sample_spec* s,
+                              std::string& msg) {
+    if (!t || !p) {
+        msg = "table and predicates must not be NULL";
+        return GACE_EINVAL;
+    }
+    if (gace_status st = check_spec(s, msg)) return st;
+    if (t->n_cols && !t->cols) {
+        msg = "table has columns but a NULL column array";
+        return GACE_EINVAL;
+    }
+    for (uint32_t c = 0; c < t->n_cols; ++c) {
+        const gace_column& col = t->cols[c];
+        if (col.dtype < GACE_I32 || col.dtype > GACE_F32) {
+            msg = "column " + std::to_string(c) + " has an unknown dtype";
+            return GACE_EINVAL;
+        }
+        if (t->n_rows && !col.data) {
+            msg = "column " + std::to_string(c) + " has a NULL data pointer";
+            return GACE_EINVAL;
+        }
+        if (((uintptr_t)col.data) & 15u) {
+            msg = "column " + std::to_string(c) + " is not 16-byte aligned";
+            return GACE_EINVAL;
+        }
+    }
+    if (p->n_preds > kMaxPredsPerReq) {
+        msg = "more than 65536 predicates in one request";
+        return GACE_EINVAL;
+    }
+    if (p->n_preds && (!p->pred_off || !p->terms)) {
+        msg = "predicates with a NULL term or offset array";
+        return GACE_EINVAL;
+    }
+    if (p->n_preds && p->pred_off[0] != 0) {
+        msg = "pred_off[0] must be 0";
+        return GACE_EINVAL;
+    }
+    for (uint32_t q = 0; q < p->n_preds; ++q) {
+        const uint32_t a = p->pred_off[q], b = p->pred_off[q + 1];
+        if (b <= a || b - a > kMaxTermsPerPred) {
+            msg = "predicate " + std::to_string(q) + " must have 1..16 terms";
+            return GACE_EINVAL;
+        }
+        for (uint32_t i = a; i < b; ++i) {
+            const gace_term& tm = p->terms[i];
+            if (tm.col >= t->n_cols) {
+                msg = "term column index out of range";
+                return GACE_EINVAL;
+            }
+            if (tm.op == GACE_RANGE) {
+                if (tm.n_vals != 2) { msg = "RANGE needs exactly 2 values"; return GACE_EINVAL; }
+            } else if (tm.op == GACE_EQ) {
+                if (tm.n_vals != 1) { msg = "EQ needs exactly 1 value"; return GACE_EINVAL; }
+            } else if (tm.op == GACE_IN) {
+                if (tm.n_vals < 1 || tm.n_vals > kMaxInVals) { msg = "IN needs 1..8 values"; return GACE_EINVAL; }
+            } else {
+                msg = "unknown term operator";
+                return GACE_EINVAL;
+            }
+            if (t->cols[tm.col].dtype == GACE_F32)
+                for (uint32_t k = 0; k < tm.n_vals; ++k)
+                    if (std::isnan(f32_of(tm.v[k]))) { msg = "NaN float bound"; return GACE_EINVAL; }
+        }
+    }
+    return GACE_OK;
+}
+
+static gace_status check_side(const gace_keys* k, const char* name, std::string& msg) {
+    if (!k) { msg = std::string(name) + " is NULL"; return GACE_EINVAL; }
+    if (k->n && !k->keys) { msg = std::string(name) + " has keys but a NULL pointer"; return GACE_EINVAL; }
+    if (((uintptr_t)k->keys) & 7u) { msg = std::string(name) + " keys are not 8-byte aligned"; return GACE_EINVAL; }
+    if (k->n > 0xFFFFFFFFull) { msg = std::string(name) + " has more than 2^32 - 1 keys"; return GACE_EINVAL; }
+    return check_spec(&k->spec, msg);
+}
+
+gace_status check_join(const gace_keys* R, const gace_keys* S, std::string& msg) {
+    if (gace_status st = check_side(R, "R", msg)) return st;
+    if (gace_status st = check_side(S, "S", msg)) return st;
+    if (R->n && S->n && (u128)R->n * (u128)S->n >= ((u128)1 << 64)) {
+        msg = "n_R * n_S >= 2^64: the join size could overflow 64 bits";
+        return GACE_EOVERFLOW;
+    }
+    return GACE_OK;
+}
+
+gace_status check_request(const gace_request* r, std::string& msg) {
+    if (!r) { msg = "NULL request"; return GACE_EINVAL; }
+    if (r->kind == GACE_REQ_SELECTIVITY) {
+        if (gace_status st = check_selectivity(&r->table, &r->preds, &r->spec, msg)) return st;
+        if (r->preds.n_preds && !r->counts) { msg = "NULL counts output"; return GACE_EINVAL; }
+        return GACE_OK;
+    }
+    if (r->kind == GACE_REQ_JOIN) {
+        if (gace_status st = check_join(&r->R, &r->S, msg)) return st;
+        if (!r->join) { msg = "NULL join output"; return GACE_EINVAL; }
+        return GACE_OK;
+    }
+    msg = "unknown request kind";
+    return GACE_EINVAL;
+}
+
+// ------------------------------------------------------------------ intervals
+struct Iv {
+    u128 a, b;   // [a, b) on the key line; b == END means "to the end"
+};
+
+static void term_intervals(uint32_t dtype, const gace_term& t, std::vector<Iv>& out) {
+    out.clear();
+    if (dtype == GACE_I32) {
+        const int64_t lo32 = INT32_MIN, end32 = (int64_t)INT32_MAX + 1;
+        const u128 bias = (u128)1 << 31;
+        if (t.op == GACE_RANGE) {
+            const int64_t l = std::max(t.v[0], lo32), h = std::min(t.v[1], end32);
+            if (l < h) out.push_back({(u128)(l + (int64_t)bias), (u128)(h + (int64_t)bias)});
+        } else {
+            for (uint32_t i = 0; i < t.n_vals; ++i)
+                if (t.v[i] >= lo32 && t.v[i] < end32) {
+                    const u128 k = (u128)(t.v[i] + (int64_t)bias);
+                    out.push_back({k, k + 1});
+                }
+        }
+    } else if (dtype == GACE_F32) {
+        if (t.op == GACE_RANGE) {
+            const float fl = f32_of(t.v[0]), fh = f32_of(t.v[1]);
+            if (fl < fh) out.push_back({(u128)f32_key(fl), (u128)f32_key(fh)});
+        } else {
+            for (uint32_t i = 0; i < t.n_vals; ++i) {
+                const u128 k = f32_key(f32_of(t.v[i]));
+                out.push_back({k, k + 1});
+            }
+        }
+    } else {
+        const uint64_t flip = 0x8000000000000000ull;
+        if (t.op == GACE_RANGE) {
+            if (t.v[0] < t.v[1]) out.push_back({(u128)((uint64_t)t.v[0] ^ flip), (u128)((uint64_t)t.v[1] ^ flip)});
+        } else {
+            for (uint32_t i = 0; i < t.n_vals; ++i) {
+                const u128 k = (u128)((uint64_t)t.v[i] ^ flip);
+                out.push_back({k, k + 1});
+            }
+        }
+    }
+    // merge overlapping intervals (IN lists may repeat values)
+    std::sort(out.begin(), out.end(), [](const Iv& x, const Iv& y) { return x.a < y.a; });
+    size_t w = 0;
+    for (size_t i = 0; i < out.size(); ++i) {
+        if (w && out[i].a <= out[w - 1].b) {
+            if (out[i].b > out[w - 1].b) out[w - 1].b = out[i].b;
+        } else {
+            out[w++] = out[i];
+        }
+    }
+    out.resize(w);
+}
+
+// ------------------------------------------------------------------ groups
+struct BitRef {
+    const gace_table* table;
+    const gace_term* terms;   // the predicate's terms
+    uint32_t n_terms;
+};
+
+struct ColBuild {
+    uint32_t col;
+    ColProg prog;
+    std::vector<uint64_t> masks;
+    std::vector<uint64_t> bnd;   // boundaries (stored as u32 or u64)
+    bool wide;
+};
+
+static uint32_t align_up(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
+
+// Build the programs of one group of <= 64 bits.  Returns the group descriptor
+// (offsets relative to its own table region) and appends its ColProgs.
+static void build_group(const std::vector<BitRef>& bits, const gace_table* table, GroupDesc& G,
+                        std::vector<ColProg>& cols_out, std::vector<uint8_t>& tab_out) {
+    const uint32_t nb = (uint32_t)bits.size();
+    uint64_t base = nb == 64 ? ~0ull : ((1ull << nb) - 1);
+    // referenced columns, in ascending order
+    std::vector<uint32_t> refcols;
+    for (const BitRef& b : bits)
+        for (uint32_t i = 0; i < b.n_terms; ++i) refcols.push_back(b.terms[i].col);
+    std::sort(refcols.begin(), refcols.end());
+    refcols.erase(std::unique(refcols.begin(), refcols.end()), refcols.end());
+
+    std::vector<ColBuild> builds;
+    std::vector<Iv> iv;
+    for (uint32_t col : refcols) {
+        const uint32_t dt = table->cols[col].dtype;
+        const bool wide = dt == GACE_I64;
+        const u128 END = wide ? ((u128)1 << 64) : ((u128)1 << 32);
+        // per bit: the term intervals on this column
+        std::vector<std::vector<std::vector<Iv>>> per_bit(nb);
+        std::vector<u128> B;
+        for (uint32_t i = 0; i < nb; ++i)
+            for (uint32_t t = 0; t < bits[i].n_terms; ++t)
+                if (bits[i].terms[t].col == col) {
+                    term_intervals(dt, bits[i].terms[t], iv);
+                    for (const Iv& x : iv) {
+                        if (x.a > 0) B.push_back(x.a);
+                        if (x.b < END) B.push_back(x.b);
+                    }
+                    per_bit[i].push_back(iv);
+                }
+        std::sort(B.begin(), B.end());
+        B.erase(std::unique(B.begin(), B.end()), B.end());
+        const uint32_t m = (uint32_t)B.size();
+        auto idx = [&](u128 x) -> uint32_t {
+            if (x >= END) return m + 1;
+            return (uint32_t)(std::upper_bound(B.begin(), B.end(), x) - B.begin());
+        };
+        // acceptance: bit set on interval j when all the bit's terms on this column hold there
+        std::vector<uint64_t> mask(m + 1, 0);
+        std::vector<uint64_t> diff(m + 2, 0);
+        uint64_t no_term = 0;
+        std::vector<uint8_t> acc, tacc;
+        for (uint32_t i = 0; i < nb; ++i) {
+            const uint64_t bit = 1ull << i;
+            if (per_bit[i].empty()) { no_term |= bit; continue; }
+            if (per_bit[i].size() == 1) {
+                for (const Iv& x : per_bit[i][0]) {
+                    diff[idx(x.a)] ^= bit;
+                    diff[idx(x.b)] ^= bit;
+                }
+                continue;
+            }
+            acc.assign(m + 1, 1);
+            for (const auto& term : per_bit[i]) {
+                tacc.assign(m + 2, 0);
+                for (const Iv& x : term) {
+                    tacc[idx(x.a)] ^= 1;
+                    tacc[idx(x.b)] ^= 1;
+                }
+                uint8_t run = 0;
+                for (uint32_t j = 0; j <= m; ++j) {
+                    run ^= tacc[j];
+                    acc[j] &= run;
+                }
+            }
+            for (uint32_t j = 0; j <= m; ++j)
+                if (acc[j]) mask[j] |= bit;
+        }
+        uint64_t run = 0;
+        for (uint32_t j = 0; j <= m; ++j) {
+            run ^= diff[j];
+            mask[j] |= run | no_term;
+        }
+        if (m == 0) {            // constant column: fold into the base mask
+            base &= mask[0];
+            continue;
+        }
+        ColBuild cb;
+        cb.col = col;
+        cb.wide = wide;
+        std::memset(&cb.prog, 0, sizeof(cb.prog));
+        cb.prog.data = table->cols[col].data;
+        cb.prog.xform = dt == GACE_I32 ? XF_I32 : (dt == GACE_F32 ? XF_F32 : XF_I64);
+        cb.masks = std::move(mask);
+        cb.bnd.resize(m);
+        for (uint32_t j = 0; j < m; ++j) cb.bnd[j] = (uint64_t)B[j];
+        builds.push_back(std::move(cb));
+    }
+
+    // choose LUT or RANK per column within the LDS budget
+    auto rank_bytes = [](const ColBuild& c) {
+        return align_up((uint32_t)c.masks.size() * 8, 8) + align_up((uint32_t)c.bnd.size() * (c.wide ? 8 : 4), 8);
+    };
+    auto lut_entries = [](const ColBuild& c) -> uint64_t {
+        if (c.wide) return ~0ull;
+        return c.bnd.back() - c.bnd.front() + 2;
+    };
+    uint32_t total = 0;
+    for (const ColBuild& c : builds) total += rank_bytes(c);
+    std::vector<bool> use_lut(builds.size(), false);
+    for (size_t i = 0; i < builds.size(); ++i) {
+        const uint64_t e = lut_entries(builds[i]);
+        if (e > kLutMaxEntries) continue;
+        const uint32_t lb = align_up((uint32_t)e * 8, 8);
+        if (total - rank_bytes(builds[i]) + lb <= kGroupTabBudget) {
+            total = total - rank_bytes(builds[i]) + lb;
+            use_lut[i] = true;
+        }
+    }
+
+    std::vector<uint8_t> tab;
+    auto put = [&](const void* p, size_t n) -> uint32_t {
+        const uint32_t off = align_up((uint32_t)tab.size(), 8);
+        tab.resize(off + n);
+        std::memcpy(tab.data() + off, p, n);
+        return off;
+    };
+    G.col_begin = (uint32_t)cols_out.size();
+    for (size_t i = 0; i < builds.size(); ++i) {
+        ColBuild& c = builds[i];
+        ColProg P = c.prog;
+        if (use_lut[i]) {
+            const uint32_t lo = (uint32_t)c.bnd.front() - 1u, hi = (uint32_t)c.bnd.back();
+            std::vector<uint64_t> lut(hi - lo + 1);
+            uint32_t j = 0;   // interval index of key lo + e
+            for (uint64_t e = 0; e < lut.size(); ++e) {
+                const uint64_t key = (uint64_t)lo + e;
+                while (j < c.bnd.size() && c.bnd[j] <= key) ++j;
+                lut[e] = c.masks[j];
+            }
+            P.kind = CP_LUT32;
+            P.lo = lo;
+            P.hi = hi;
+            P.mask_off = put(lut.data(), lut.size() * 8);
+        } else {
+            P.kind = c.wide ? CP_RANK64 : CP_RANK32;
+            P.nb = (uint32_t)c.bnd.size();
+            P.step = 1;
+            while (P.step * 2 <= P.nb) P.step *= 2;
+            P.mask_off = put(c.masks.data(), c.masks.size() * 8);
+            if (c.wide) {
+                P.bnd_off = put(c.bnd.data(), c.bnd.size() * 8);
+            } else {
+                std::vector<uint32_t> b32(c.bnd.begin(), c.bnd.end());
+                P.bnd_off = put(b32.data(), b32.size() * 4);
+            }
+        }
+        cols_out.push_back(P);
+    }
+    G.col_end = (uint32_t)cols_out.size();
+    tab.resize(align_up((uint32_t)tab.size(), 16));
+    G.base_mask = base;
+    G.n_used = nb;
+    G.tab_bytes = (uint32_t)tab.size();
+    tab_out = std::move(tab);
+}
+
+// ------------------------------------------------------------------ batch
+static uint32_t log2u(uint32_t x) {
+    uint32_t l = 0;
+    while ((1u << l) < x) ++l;
+    return l;
+}
+
+static uint64_t kept_upper(uint64_t nb, uint64_t thr) {
+    if (thr >= kThrAll) return nb;
+    const double p = (double)thr / 4294967296.0;
+    const double mu = (double)nb * p, sd = std::sqrt((double)nb * p * (1.0 - p));
+    const double hi = std::ceil(mu + 12.0 * sd + 16.0);
+    return hi >= (double)nb ? nb : (uint64_t)hi;
+}
+
+static uint64_t bpi_for(uint64_t thr, uint32_t log2B, uint32_t item_rows) {
+    const double p = thr >= kThrAll ? 1.0 : (double)thr / 4294967296.0;
+    if (p <= 0.0) return 0;
+    double want = (double)item_rows / ((double)(1ull << log2B) * p);
+    uint64_t b = want < 1.0 ? 1 : (uint64_t)want;
+    if (b > 64) b = (b + 63) / 64 * 64;   // whole 64-block decision chunks
+    if (b > (1ull << 30)) b = 1ull << 30;
+    return b;
+}
+
+void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& opt, CompiledBatch& out) {
+    out = CompiledBatch();
+    out.status.assign(n, GACE_OK);
+    out.errors.assign(n, std::string());
+
+    struct ScanReq { uint32_t req; uint64_t thr; };
+    std::map<std::vector<uint64_t>, uint32_t> scan_of;
+    std::vector<std::vector<ScanReq>> scan_reqs;
+    std::vector<uint32_t> join_reqs;
+    for (uint32_t i = 0; i < n; ++i) {
+        std::string msg;
+        gace_status st = check_request(&reqs[i], msg);
+        out.status[i] = st;
+        out.errors[i] = msg;
+        if (st != GACE_OK) continue;
+        const gace_request& r = reqs[i];
+        if (r.kind == GACE_REQ_JOIN) {
+            join_reqs.push_back(i);
+            continue;
+        }
+        const uint32_t B = r.spec.block_rows;
+        std::vector<uint64_t> key = {r.table.n_rows, r.table.table_id, r.spec.seed, B, r.table.n_cols};
+        for (uint32_t c = 0; c < r.table.n_cols; ++c) {
+            key.push_back((uint64_t)(uintptr_t)r.table.cols[c].data);
+            key.push_back(r.table.cols[c].dtype);
+        }
+        auto it = scan_of.find(key);
+        uint32_t s;
+        if (it == scan_of.end()) {
+            s = (uint32_t)scan_reqs.size();
+            scan_of.emplace(key, s);
+            scan_reqs.emplace_back();
+        } else {
+            s = it->second;
+        }
+        scan_reqs[s].push_back({i, rate_threshold(r.spec.rate)});
+    }
+
+    // ---- selectivity scans
+    std::vector<ScanDesc> scans;
+    std::vector<GroupDesc> groups;
+    std::vector<ColProg> cols;
+    std::vector<uint32_t> slots;
+    std::vector<uint64_t> rthr;
+    std::vector<uint32_t> rcum;
+    std::vector<std::vector<uint8_t>> tabs;
+    uint32_t n_counts = 0, n_hist = 0;
+    for (uint32_t s = 0; s < scan_reqs.size(); ++s) {
+        auto& sr = scan_reqs[s];
+        std::stable_sort(sr.begin(), sr.end(), [](const ScanReq& x, const ScanReq& y) { return x.thr > y.thr; });
+        const gace_request& r0 = reqs[sr[0].req];
+        ScanDesc S;
+        std::memset(&S, 0, sizeof(S));
+        S.n_rows = r0.table.n_rows;
+        S.seed = r0.spec.seed;
+        S.thr_max = sr[0].thr;
+        S.log2B = log2u(r0.spec.block_rows);
+        S.n_blocks = (S.n_rows + (1ull << S.log2B) - 1) >> S.log2B;
+        S.table_id = r0.table.table_id;
+        S.req_begin = (uint32_t)rthr.size();
+        S.n_req = (uint32_t)sr.size();
+        S.hist_off = n_hist;
+        n_hist += 2 * (S.n_req + 1);
+        S.group_begin = (uint32_t)groups.size();
+
+        std::vector<BitRef> bits;
+        std::vector<uint32_t> bit_slot;
+        std::vector<bool> used_col(r0.table.n_cols, false);
+        uint32_t cum = 0;
+        rcum.push_back(0);
+        for (uint32_t q = 0; q < sr.size(); ++q) {
+            const gace_request& r = reqs[sr[q].req];
+            rthr.push_back(sr[q].thr);
+            SelOut so;
+            so.req = sr[q].req;
+            so.scan = s;
+            so.rank = q;
+            so.count_off = n_counts;
+            so.n_preds = r.preds.n_preds;
+            out.sel.push_back(so);
+            for (uint32_t p = 0; p < r.preds.n_preds; ++p) {
+                const uint32_t a = r.preds.pred_off[p], b = r.preds.pred_off[p + 1];
+                bits.push_back({&r.table, r.preds.terms + a, b - a});
+                bit_slot.push_back(n_counts + p);
+                for (uint32_t t = a; t < b; ++t) used_col[r.preds.terms[t].col] = true;
+            }
+            n_counts += r.preds.n_preds;
+            cum += r.preds.n_preds;
+            if (q + 1 < sr.size()) rcum.push_back(cum);
+        }
+        rcum.push_back(cum);
+        // rcum for this scan has n_req + 1 entries; rthr has n_req
+        for (uint32_t c = 0; c < r0.table.n_cols; ++c)
+            if (used_col[c]) S.row_bytes += r0.table.cols[c].dtype == GACE_I64 ? 8 : 4;
+
+        for (uint32_t g0 = 0; g0 < bits.size(); g0 += 64) {
+            const uint32_t g1 = std::min<uint32_t>((uint32_t)bits.size(), g0 + 64);
+            std::vector<BitRef> gb(bits.begin() + g0, bits.begin() + g1);
+            GroupDesc G;
+            std::memset(&G, 0, sizeof(G));
+            std::vector<uint8_t> tab;
+            build_group(gb, &r0.table, G, cols, tab);
+            G.slot_index = (uint32_t)slots.size();
+            for (uint32_t i = g0; i < g0 + 64; ++i) slots.push_back(i < g1 ? bit_slot[i] : 0);
+            groups.push_back(G);
+            tabs.push_back(std::move(tab));
+        }
+        S.n_groups = (uint32_t)groups.size() - S.group_begin;
+        scans.push_back(S);
+    }
+    // the reqcum array interleaves per scan: entries [req_begin + scan_index, ...) -- keep it simple by
+    // rebuilding it with explicit per-scan offsets
+    std::vector<uint32_t> rcum_flat;
+    {
+        size_t pos = 0;
+        for (uint32_t s = 0; s < scans.size(); ++s) {
+            const uint32_t nr = scans[s].n_req;
+            scans[s].req_begin = (uint32_t)rcum_flat.size();   // same start for thresholds (copied below)
+            for (uint32_t i = 0; i <= nr; ++i) rcum_flat.push_back(rcum[pos + i]);
+            pos += nr + 1;
+        }
+    }
+    // thresholds laid out with the same per-scan start as rcum_flat (n_req + 1 stride, last unused)
+    std::vector<uint64_t> rthr_flat;
+    {
+        size_t pos = 0;
+        for (uint32_t s = 0; s < scans.size(); ++s) {
+            const uint32_t nr = scans[s].n_req;
+            for (uint32_t i = 0; i < nr; ++i) rthr_flat.push_back(rthr[pos + i]);
+            rthr_flat.push_back(0);
+            pos += nr;
+        }
+    }
+
+    // ---- joins
+    std::vector<JoinDesc> joins;
+    uint64_t sketch_bytes = 0;
+    for (uint32_t j = 0; j < join_reqs.size(); ++j) {
+        const gace_request& r = reqs[join_reqs[j]];
+        JoinDesc J;
+        std::memset(&J, 0, sizeof(J));
+        uint64_t U = 0;
+        const gace_keys* sides[2] = {&r.R, &r.S};
+        for (int s = 0; s < 2; ++s) {
+            JoinSide& D = J.side[s];
+            D.keys = sides[s]->keys;
+            D.n = sides[s]->n;
+            D.seed = sides[s]->spec.seed;
+            D.thr = rate_threshold(sides[s]->spec.rate);
+            D.log2B = log2u(sides[s]->spec.block_rows);
+            D.n_blocks = (D.n + (1ull << D.log2B) - 1) >> D.log2B;
+            D.table_id = sides[s]->table_id;
+            U += std::min<uint64_t>(D.n, kept_upper(D.n_blocks, D.thr) << D.log2B);
+        }
+        uint64_t cap = 2048;
+        while (cap < 2 * U) cap <<= 1;
+        J.cap_max = cap;
+        J.acc = j;
+        J.sketch_off = sketch_bytes;
+        out.table_bytes_max += cap * sizeof(Slot);
+        joins.push_back(J);
+        JoinOut jo;
+        jo.req = join_reqs[j];
+        jo.join = j;
+        out.joins.push_back(jo);
+    }
+
+    // ---- items
+    std::vector<Item> sketch_items, size_items, init_items, scan_items, build_items, final_items;
+    for (uint32_t j = 0; j < joins.size(); ++j) {
+        JoinDesc& J = joins[j];
+        uint32_t n_sketch = 0, n_build = 0;
+        for (uint32_t s = 0; s < 2; ++s) {
+            const JoinSide& D = J.side[s];
+            if (D.thr == 0 || D.n == 0) continue;
+            const double p = D.thr >= kThrAll ? 1.0 : (double)D.thr / 4294967296.0;
+            const double rows = (double)D.n * p;
+            // sketch: at most kSketchRowsPerJoin / 2 items per side
+            uint64_t want = (uint64_t)std::ceil(rows / (double)opt.item_rows);
+            if (want < 1) want = 1;
+            if (want > kSketchRowsPerJoin / 2) want = kSketchRowsPerJoin / 2;
+            uint64_t bpi = (D.n_blocks + want - 1) / want;
+            if (bpi > 64) bpi = (bpi + 63) / 64 * 64;
+            for (uint64_t b = 0; b < D.n_blocks; b += bpi) {
+                Item it = {IT_JSKETCH, j, s, n_sketch++, b, std::min(D.n_blocks, b + bpi)};
+                sketch_items.push_back(it);
+            }
+            const uint64_t bb = bpi_for(D.thr, D.log2B, opt.item_rows);
+            for (uint64_t b = 0; b < D.n_blocks; b += bb) {
+                Item it = {IT_JBUILD, j, s, 0, b, std::min(D.n_blocks, b + bb)};
+                build_items.push_back(it);
+                ++n_build;
+            }
+        }
+        J.n_sketch = n_sketch;
+        J.n_build = n_build;
+        sketch_bytes += (uint64_t)n_sketch << kHllBits;
+        size_items.push_back({IT_JSIZE, j, 0, 0, 0, 0});
+        for (uint32_t c = 0; c < kSlotChunks; ++c) {
+            init_items.push_back({IT_JINIT, j, 0, c, 0, 0});
+            final_items.push_back({IT_JFINAL, j, 0, c, 0, 0});
+        }
+        if (j + 1 < joins.size()) joins[j + 1].sketch_off = sketch_bytes;
+    }
+    for (uint32_t s = 0; s < scans.size(); ++s) {
+        const ScanDesc& S = scans[s];
+        const uint64_t bb = bpi_for(S.thr_max, S.log2B, opt.item_rows);
+        if (bb == 0) continue;
+        for (uint64_t b = 0; b < S.n_blocks; b += bb) {
+            Item it = {IT_SCAN, s, 0, 0, b, std::min(S.n_blocks, b + bb)};
+            scan_items.push_back(it);
+        }
+    }
+    // larger scans first so the tail of the queue is short items
+    std::stable_sort(scan_items.begin(), scan_items.end(), [&](const Item& x, const Item& y) {
+        return scans[x.idx].row_bytes * scans[x.idx].thr_max > scans[y.idx].row_bytes * scans[y.idx].thr_max;
+    });
+    for (auto* v : {&sketch_items, &size_items, &init_items, &scan_items, &build_items, &final_items})
+        out.items.insert(out.items.end(), v->begin(), v->end());
+
+    // ---- plan blob
+    PlanHdr H;
+    std::memset(&H, 0, sizeof(H));
+    H.n_scans = (uint32_t)scans.size();
+    H.n_groups = (uint32_t)groups.size();
+    H.n_cols = (uint32_t)cols.size();
+    H.n_joins = (uint32_t)joins.size();
+    H.n_counts = n_counts;
+    H.n_hist = n_hist;
+    H.n_items = (uint32_t)out.items.size();
+    std::vector<uint8_t>& blob = out.plan;
+    blob.assign(sizeof(PlanHdr), 0);
+    auto put = [&](const void* p, size_t nbytes) -> uint32_t {
+        const uint32_t off = align_up((uint32_t)blob.size(), 16);
+        blob.resize(off + nbytes);
+        if (nbytes) std::memcpy(blob.data() + off, p, nbytes);
+        return off;
+    };
+    // group tables first so their offsets are known when groups are written
+    for (uint32_t g = 0; g < groups.size(); ++g) groups[g].tab_off = put(tabs[g].data(), tabs[g].size());
+    H.scans_off = put(scans.data(), scans.size() * sizeof(ScanDesc));
+    H.groups_off = put(groups.data(), groups.size() * sizeof(GroupDesc));
+    H.cols_off = put(cols.data(), cols.size() * sizeof(ColProg));
+    H.slots_off = put(slots.data(), slots.size() * sizeof(uint32_t));
+    H.reqthr_off = put(rthr_flat.data(), rthr_flat.size() * sizeof(uint64_t));
+    H.reqcum_off = put(rcum_flat.data(), rcum_flat.size() * sizeof(uint32_t));
+    H.joins_off = put(joins.data(), joins.size() * sizeof(JoinDesc));
+    blob.resize(align_up((uint32_t)blob.size(), 16));
+    H.total_bytes = (uint32_t)blob.size();
+    std::memcpy(blob.data(), &H, sizeof(H));
+
+    out.scans = scans;
+    out.jdesc = joins;
+    out.n_counts = n_counts;
+    out.n_hist = n_hist;
+    out.sketch_bytes = sketch_bytes;
+}
+
+}  // namespace gace

@@ -1,0 +1,57 @@
+// compile.h -- host-side validation and compilation of probe requests into a
+// device plan (see plan.h).  No HIP calls: usable without a GPU.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gace.h"
+#include "plan.h"
+
+namespace gace {
+
+uint64_t rate_threshold(double rate);
+
+gace_status check_spec(const gace_sample_spec* s, std::string& msg);
+gace_status check_selectivity(const gace_table* t, const gace_predicates* p, const gace_sample_spec* s,
+                              std::string& msg);
+gace_status check_join(const gace_keys* R, const gace_keys* S, std::string& msg);
+gace_status check_request(const gace_request* r, std::string& msg);
+
+struct CompileOptions {
+    uint32_t item_rows = 65536;      // target sampled rows per work item
+};
+
+// host bookkeeping that maps plan results back to the requests
+struct SelOut {
+    uint32_t req;                    // index in the caller's request array
+    uint32_t scan;
+    uint32_t rank;                   // position among the scan's requests (threshold descending)
+    uint32_t count_off;
+    uint32_t n_preds;
+};
+
+struct JoinOut {
+    uint32_t req;
+    uint32_t join;                   // index of the JoinDesc / JoinAcc
+};
+
+struct CompiledBatch {
+    std::vector<uint8_t> plan;       // PlanHdr + descriptors + tables
+    std::vector<Item> items;
+    std::vector<SelOut> sel;
+    std::vector<JoinOut> joins;
+    std::vector<ScanDesc> scans;     // host copies
+    std::vector<JoinDesc> jdesc;
+    std::vector<gace_status> status; // per caller request (validation result)
+    std::vector<std::string> errors;
+    uint32_t n_counts = 0, n_hist = 0;
+    uint64_t sketch_bytes = 0;       // HLL rows
+    uint64_t table_bytes_max = 0;    // sum of the largest hash tables the joins may need
+};
+
+// Validate every request; compile the valid ones.  Never throws.
+void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& opt, CompiledBatch& out);
+
+}  // namespace gace

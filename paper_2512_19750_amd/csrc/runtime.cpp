@@ -1,0 +1,582 @@
+// runtime.cpp -- context, workspace, batch execution and the public C ABI of
+// the plain and batched paths.
+#include "runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "plan.h"
+
+extern "C" {
+hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,
+                            hipStream_t stream);
+hipError_t gace_launch_batch(const void* args, uint32_t grid, hipStream_t stream);
+uint32_t gace_batch_lds_bytes(void);
+}
+
+namespace gace {
+
+// kernel argument block (must match kernels.hip)
+struct BatchArgsHost {
+    const uint8_t* plan;
+    const Item* items;
+    uint32_t* head;
+    unsigned long long* counts;
+    unsigned long long* hist;
+    JoinAcc* accs;
+    uint8_t* sketch;
+    uint8_t* arena_base;
+    Arena* arena;
+    uint32_t count_mode;
+    uint32_t cache_slots;
+    uint64_t force_cap;
+};
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+static gace_status hip_fail(hipError_t e, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return GACE_EDEVICE;
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+static gace_schedule default_schedule() {
+    gace_schedule s;
+    std::memset(&s, 0, sizeof(s));
+    s.wg_threads = 256;
+    s.wgs_per_cu = 2;
+    s.item_rows = 65536;
+    s.count_mode = 0;
+    s.join_cache_slots = 2048;
+    return s;
+}
+
+static bool valid_schedule(const gace_schedule& s) {
+    const uint32_t cs = s.join_cache_slots;
+    return s.wg_threads == 256 && s.wgs_per_cu >= 1 && s.wgs_per_cu <= 8 && s.item_rows >= 1024 &&
+           s.count_mode <= 2 && (cs == 0 || (cs <= 2048 && (cs & (cs - 1)) == 0));
+}
+
+static BatchArgsHost make_args(gace_ctx* c, uint64_t force_cap) {
+    BatchArgsHost a;
+    a.plan = c->d_plan;
+    a.items = c->d_items;
+    a.head = c->d_head;
+    a.counts = c->d_counts;
+    a.hist = c->d_hist;
+    a.accs = c->d_accs;
+    a.sketch = c->d_sketch;
+    a.arena_base = c->d_arena_base;
+    a.arena = c->d_arena;
+    a.count_mode = c->sched.count_mode;
+    a.cache_slots = c->sched.join_cache_slots;
+    a.force_cap = force_cap;
+    return a;
+}
+
+static uint32_t grid_of(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.wgs_per_cu; }
+
+static gace_status launch_direct(gace_ctx* c, hipStream_t st, uint64_t force_cap) {
+    BatchArgsHost a = make_args(c, force_cap);
+    HIP_TRY(gace_launch_init(c->d_plan, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st), "init kernel");
+    HIP_TRY(gace_launch_batch(&a, grid_of(c), st), "batch kernel");
+    return GACE_OK;
+}
+
+static void drop_graph(gace_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+static gace_status ensure_graph(gace_ctx* c) {
+    if (c->graph_exec && std::memcmp(&c->graph_sched, &c->sched, sizeof(gace_schedule)) == 0) return GACE_OK;
+    drop_graph(c);
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    gace_status st = launch_direct(c, c->cap_stream, 0);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != GACE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    c->graph = g;
+    HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0), "graph instantiate");
+    c->graph_sched = c->sched;
+    return GACE_OK;
+}
+
+// upload a compiled batch, launch it and queue the result download on st
+gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool use_graph, uint64_t force_cap) {
+    const uint64_t plan_b = cb.plan.size(), items_b = cb.items.size() * sizeof(Item);
+    const uint64_t accs_b = cb.jdesc.size() * sizeof(JoinAcc);
+    auto too_big = [&](const char* what, uint64_t need, uint64_t cap) {
+        set_error(std::string("workspace region for ") + what + " too small: need " + std::to_string(need) +
+                  " bytes, have " + std::to_string(cap));
+        return GACE_ENOMEM;
+    };
+    if (plan_b > kPlanCap) return too_big("the plan", plan_b, kPlanCap);
+    if (items_b > kItemsCap) return too_big("work items", items_b, kItemsCap);
+    if (cb.n_counts * 8ull > kCountsCap) return too_big("counts", cb.n_counts * 8ull, kCountsCap);
+    if (cb.n_hist * 8ull > kHistCap) return too_big("sample histograms", cb.n_hist * 8ull, kHistCap);
+    if (accs_b > kAccsCap) return too_big("join accumulators", accs_b, kAccsCap);
+    if (cb.sketch_bytes > kSketchCap) return too_big("join sketches", cb.sketch_bytes, kSketchCap);
+
+    std::memcpy(c->h_stage, cb.plan.data(), plan_b);
+    std::memcpy(c->h_stage + kPlanCap, cb.items.data(), items_b);
+    HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, plan_b, hipMemcpyHostToDevice, st), "plan upload");
+    if (items_b)
+        HIP_TRY(hipMemcpyAsync(c->d_items, c->h_stage + kPlanCap, items_b, hipMemcpyHostToDevice, st), "item upload");
+    HIP_TRY(hipEventRecord(c->ev0, st), "event");
+    if (use_graph && force_cap == 0) {
+        if (gace_status s = ensure_graph(c)) return s;
+        HIP_TRY(hipGraphLaunch(c->graph_exec, st), "graph launch");
+    } else {
+        if (gace_status s = launch_direct(c, st, force_cap)) return s;
+    }
+    HIP_TRY(hipEventRecord(c->ev1, st), "event");
+    uint8_t* hc = c->h_result;
+    uint8_t* hh = hc + kCountsCap;
+    uint8_t* ha = hh + kHistCap;
+    if (cb.n_counts)
+        HIP_TRY(hipMemcpyAsync(hc, c->d_counts, cb.n_counts * 8ull, hipMemcpyDeviceToHost, st), "counts download");
+    if (cb.n_hist)
+        HIP_TRY(hipMemcpyAsync(hh, c->d_hist, cb.n_hist * 8ull, hipMemcpyDeviceToHost, st), "hist download");
+    if (accs_b) HIP_TRY(hipMemcpyAsync(ha, c->d_accs, accs_b, hipMemcpyDeviceToHost, st), "join download");
+    HIP_TRY(hipEventRecord(c->ev_done, st), "event");
+    return GACE_OK;
+}
+
+// after the batch's done event: write per-request outputs
+gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
+                            hipStream_t st, uint64_t force_cap) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_kernel_ms = ms;
+    const uint8_t* hc = c->h_result;
+    const unsigned long long* counts = (const unsigned long long*)hc;
+    const unsigned long long* hist = (const unsigned long long*)(hc + kCountsCap);
+    const JoinAcc* accs = (const JoinAcc*)(hc + kCountsCap + kHistCap);
+    uint64_t alg = 0, rp = 0;
+    for (const ScanDesc& S : cb.scans) {
+        uint64_t kept_rows = 0;
+        for (uint32_t k = 1; k <= S.n_req; ++k) kept_rows += hist[S.hist_off + 2 * k];
+        alg += kept_rows * S.row_bytes;
+    }
+    for (const SelOut& so : cb.sel) {
+        const gace_request& r = reqs[so.req];
+        const ScanDesc& S = cb.scans[so.scan];
+        uint64_t rows = 0, blocks = 0;
+        for (uint32_t k = so.rank + 1; k <= S.n_req; ++k) {
+            rows += hist[S.hist_off + 2 * k];
+            blocks += hist[S.hist_off + 2 * k + 1];
+        }
+        for (uint32_t p = 0; p < so.n_preds; ++p) r.counts[p] = counts[so.count_off + p];
+        if (r.info) {
+            r.info->sampled_rows = rows;
+            r.info->kept_blocks = blocks;
+        }
+        rp += rows * so.n_preds;
+        if (per_req) per_req[so.req] = GACE_OK;
+    }
+    // copy join accumulators first: a rerun below reuses the result buffer
+    std::vector<JoinAcc> acc_copy(accs, accs + cb.jdesc.size());
+    gace_status worst = GACE_OK;
+    for (const JoinOut& jo : cb.joins) {
+        const JoinAcc& A = acc_copy[jo.join];
+        const gace_request& r = reqs[jo.req];
+        gace_status s = GACE_OK;
+        c->learned_cap[join_identity(r)] = A.cap;
+        if (A.status == 1 && force_cap == 0) {
+            // the sketch-sized table filled up: rerun this join alone at the bound capacity
+            CompiledBatch one;
+            CompileOptions opt;
+            opt.item_rows = c->sched.item_rows;
+            compile_batch(&r, 1, opt, one);
+            gace_status ps = GACE_OK;
+            s = run_compiled(c, one, &r, &ps, st, false, one.jdesc[0].cap_max);
+            if (s == GACE_OK) s = ps;
+        } else if (A.status == 1) {
+            set_error("join hash table overflow at the bound capacity");
+            s = GACE_EDEVICE;
+        } else if (A.status == 2) {
+            set_error("workspace arena too small for the join hash tables of this batch");
+            s = GACE_ENOMEM;
+        } else {
+            r.join->join_card = A.join;
+            r.join->ndv_R = A.ndv[0];
+            r.join->ndv_S = A.ndv[1];
+            r.join->n_R = A.n[0];
+            r.join->n_S = A.n[1];
+            alg += 8ull * (A.n[0] + A.n[1]);
+        }
+        if (per_req) per_req[jo.req] = s;
+        if (s != GACE_OK && worst == GACE_OK) worst = s;
+    }
+    c->last_alg_bytes = alg;
+    c->last_rows_preds = rp;
+    return worst;
+}
+
+gace_status run_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
+                         hipStream_t st, bool use_graph, uint64_t force_cap) {
+    if (gace_status s = launch_compiled(c, cb, st, use_graph, force_cap)) return s;
+    HIP_TRY(hipEventSynchronize(c->ev_done), "synchronize");
+    return finish_compiled(c, cb, reqs, per_req, st, force_cap);
+}
+
+std::string join_identity(const gace_request& r) {
+    std::ostringstream os;
+    os << (const void*)r.R.keys << ":" << r.R.n << ":" << r.R.table_id << ":" << r.R.spec.seed << ":"
+       << r.R.spec.rate << ":" << r.R.spec.block_rows << "|" << (const void*)r.S.keys << ":" << r.S.n << ":"
+       << r.S.table_id << ":" << r.S.spec.seed << ":" << r.S.spec.rate << ":" << r.S.spec.block_rows;
+    return os.str();
+}
+
+gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace_status* per_req, hipStream_t st,
+                         bool use_graph) {
+    CompileOptions opt;
+    opt.item_rows = c->sched.item_rows;
+    CompiledBatch cb;
+    compile_batch(reqs, n, opt, cb);
+    gace_status first = GACE_OK;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (per_req) per_req[i] = cb.status[i];
+        if (cb.status[i] != GACE_OK && first == GACE_OK) {
+            first = cb.status[i];
+            set_error("request " + std::to_string(i) + ": " + cb.errors[i]);
+        }
+    }
+    if (cb.sel.empty() && cb.joins.empty()) return first;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "set device");
+    gace_status s = run_compiled(c, cb, reqs, per_req, st, use_graph, 0);
+    if (first == GACE_OK) first = s;
+    return first;
+}
+
+std::string shape_bucket(const gace_request* reqs, uint32_t n) {
+    uint64_t sel = 0, join = 0, preds = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (reqs[i].kind == GACE_REQ_SELECTIVITY) {
+            ++sel;
+            preds += reqs[i].preds.n_preds;
+        } else {
+            ++join;
+        }
+    }
+    auto lg = [](uint64_t x) {
+        int l = 0;
+        while ((1ull << l) < x + 1) ++l;
+        return l;
+    };
+    std::ostringstream os;
+    os << "s" << lg(sel) << "j" << lg(join) << "p" << lg(preds);
+    return os.str();
+}
+
+}  // namespace gace
+
+using namespace gace;
+
+extern "C" {
+
+const char* gace_last_error(void) { return g_err.c_str(); }
+const char* gace_version(void) { return "gace-mi355x 0.1 (gfx950)"; }
+
+gace_status gace_check_request(const gace_request* req) {
+    std::string msg;
+    gace_status s = check_request(req, msg);
+    if (s != GACE_OK) set_error(msg);
+    return s;
+}
+
+gace_status gace_create(int hip_device, uint64_t workspace_bytes, gace_ctx** out) {
+    if (!out) {
+        set_error("out is NULL");
+        return GACE_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(hip_device), "set device");
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device), "device attribute");
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b), "memory info");
+    if (workspace_bytes == 0) workspace_bytes = std::min<uint64_t>(free_b / 8, 32ull << 30);
+    if (workspace_bytes < kFixedBytes + (64ull << 20)) {
+        set_error("workspace must be at least " + std::to_string(kFixedBytes + (64ull << 20)) + " bytes");
+        return GACE_EINVAL;
+    }
+    gace_ctx* c = new gace_ctx();
+    c->device = hip_device;
+    c->n_cu = cus;
+    c->sched = default_schedule();
+    hipError_t e = hipMalloc((void**)&c->ws, workspace_bytes);
+    if (e != hipSuccess) {
+        delete c;
+        set_error(std::string("workspace allocation of ") + std::to_string(workspace_bytes) + " bytes failed: " +
+                  hipGetErrorString(e));
+        return GACE_ENOMEM;
+    }
+    c->ws_bytes = workspace_bytes;
+    uint8_t* p = c->ws;
+    c->d_plan = p; p += kPlanCap;
+    c->d_items = (Item*)p; p += kItemsCap;
+    c->d_counts = (unsigned long long*)p; p += kCountsCap;
+    c->d_hist = (unsigned long long*)p; p += kHistCap;
+    c->d_accs = (JoinAcc*)p; p += kAccsCap;
+    c->d_sketch = p; p += kSketchCap;
+    c->d_head = (uint32_t*)p;
+    c->d_arena = (Arena*)(p + 256);
+    p += kMiscCap;
+    c->d_arena_base = p;
+    c->arena_bytes = workspace_bytes - kFixedBytes;
+    if (hipHostMalloc((void**)&c->h_stage, kPlanCap + kItemsCap, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_result, kCountsCap + kHistCap + kAccsCap, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        gace_destroy(c);
+        set_error("pinned staging / event / stream creation failed");
+        return GACE_EDEVICE;
+    }
+    Arena ar;
+    ar.used = 0;
+    ar.size = c->arena_bytes;
+    e = hipMemcpy(c->d_arena, &ar, sizeof(ar), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        gace_destroy(c);
+        return hip_fail(e, "arena header upload");
+    }
+    *out = c;
+    return GACE_OK;
+}
+
+gace_status gace_destroy(gace_ctx* c) {
+    if (!c) return GACE_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev_done) (void)hipEventDestroy(c->ev_done);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    if (c->h_result) (void)hipHostFree(c->h_result);
+    if (c->ws) (void)hipFree(c->ws);
+    delete c;
+    return GACE_OK;
+}
+
+gace_status gace_probe_selectivity(gace_ctx* ctx, const gace_table* table, const gace_predicates* preds,
+                                   const gace_sample_spec* spec, uint64_t* counts, gace_probe_info* info,
+                                   void* stream) {
+    if (!ctx) {
+        set_error("NULL context");
+        return GACE_EINVAL;
+    }
+    gace_request r;
+    std::memset(&r, 0, sizeof(r));
+    r.kind = GACE_REQ_SELECTIVITY;
+    if (table) r.table = *table;
+    if (preds) r.preds = *preds;
+    if (spec) {
+        r.spec = *spec;
+    } else {
+        r.spec.seed = 0;
+        r.spec.rate = 1.0;
+        r.spec.block_rows = 4096;
+    }
+    r.counts = counts;
+    r.info = info;
+    if (!table || !preds) {
+        set_error("table and predicates must not be NULL");
+        return GACE_EINVAL;
+    }
+    return run_requests(ctx, &r, 1, nullptr, (hipStream_t)stream, false);
+}
+
+gace_status gace_join_freq(gace_ctx* ctx, const gace_keys* R, const gace_keys* S, gace_join_result* out,
+                           void* stream) {
+    if (!ctx || !R || !S) {
+        set_error("NULL context or key side");
+        return GACE_EINVAL;
+    }
+    gace_request r;
+    std::memset(&r, 0, sizeof(r));
+    r.kind = GACE_REQ_JOIN;
+    r.R = *R;
+    r.S = *S;
+    r.join = out;
+    return run_requests(ctx, &r, 1, nullptr, (hipStream_t)stream, false);
+}
+
+gace_status gace_batch_run(gace_ctx* ctx, const gace_request* reqs, uint32_t n, gace_status* per_req, void* stream) {
+    if (!ctx || (n && !reqs)) {
+        set_error("NULL context or request array");
+        return GACE_EINVAL;
+    }
+    auto it = ctx->tuned.find(shape_bucket(reqs, n));
+    if (it != ctx->tuned.end()) ctx->sched = it->second;
+    return run_requests(ctx, reqs, n, per_req, (hipStream_t)stream, true);
+}
+
+gace_status gace_get_schedule(gace_ctx* ctx, gace_schedule* out) {
+    if (!ctx || !out) {
+        set_error("NULL argument");
+        return GACE_EINVAL;
+    }
+    *out = ctx->sched;
+    return GACE_OK;
+}
+
+gace_status gace_set_schedule(gace_ctx* ctx, const gace_schedule* s) {
+    if (!ctx || !s || !valid_schedule(*s)) {
+        set_error("invalid schedule");
+        return GACE_EINVAL;
+    }
+    ctx->sched = *s;
+    return GACE_OK;
+}
+
+gace_status gace_last_batch_stats(gace_ctx* ctx, double* kernel_ms, uint64_t* alg_bytes, uint64_t* rows_preds) {
+    if (!ctx) {
+        set_error("NULL context");
+        return GACE_EINVAL;
+    }
+    if (kernel_ms) *kernel_ms = ctx->last_kernel_ms;
+    if (alg_bytes) *alg_bytes = ctx->last_alg_bytes;
+    if (rows_preds) *rows_preds = ctx->last_rows_preds;
+    return GACE_OK;
+}
+
+// ------------------------------------------------------------------ autotune
+static std::string sched_json(const gace_schedule& s) {
+    std::ostringstream os;
+    os << "{\"wg_threads\": " << s.wg_threads << ", \"wgs_per_cu\": " << s.wgs_per_cu
+       << ", \"item_rows\": " << s.item_rows << ", \"count_mode\": " << s.count_mode
+       << ", \"join_cache_slots\": " << s.join_cache_slots << "}";
+    return os.str();
+}
+
+static bool parse_u32(const std::string& line, const char* key, uint32_t& v) {
+    const std::string k = std::string("\"") + key + "\": ";
+    size_t p = line.find(k);
+    if (p == std::string::npos) return false;
+    v = (uint32_t)std::strtoul(line.c_str() + p + k.size(), nullptr, 10);
+    return true;
+}
+
+// cache file: one JSON object per line {"key": "...", "schedule": {...}}
+static void load_cache(gace_ctx* c, const char* path, const std::string& prefix) {
+    if (!path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        size_t a = line.find("\"key\": \"");
+        if (a == std::string::npos) continue;
+        a += 8;
+        size_t b = line.find('"', a);
+        const std::string key = line.substr(a, b - a);
+        if (key.compare(0, prefix.size(), prefix) != 0) continue;
+        gace_schedule s = default_schedule();
+        parse_u32(line, "wg_threads", s.wg_threads);
+        parse_u32(line, "wgs_per_cu", s.wgs_per_cu);
+        parse_u32(line, "item_rows", s.item_rows);
+        parse_u32(line, "count_mode", s.count_mode);
+        parse_u32(line, "join_cache_slots", s.join_cache_slots);
+        if (valid_schedule(s)) c->tuned[key.substr(prefix.size())] = s;
+    }
+}
+
+static void save_cache(gace_ctx* c, const char* path, const std::string& prefix) {
+    if (!path) return;
+    std::map<std::string, std::string> lines;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line)) {
+            size_t a = line.find("\"key\": \"");
+            if (a == std::string::npos) continue;
+            a += 8;
+            lines[line.substr(a, line.find('"', a) - a)] = line;
+        }
+    }
+    for (auto& kv : c->tuned)
+        lines[prefix + kv.first] = "{\"key\": \"" + prefix + kv.first + "\", \"schedule\": " + sched_json(kv.second) + "}";
+    std::ofstream f(path);
+    for (auto& kv : lines) f << kv.second << "\n";
+}
+
+gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, const char* cache_path, void* stream) {
+    if (!ctx || (n && !reqs)) {
+        set_error("NULL context or request array");
+        return GACE_EINVAL;
+    }
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "device properties");
+    const std::string prefix = std::string(prop.gcnArchName) + ":" + std::to_string(ctx->n_cu) + ":";
+    const std::string bucket = shape_bucket(reqs, n);
+    load_cache(ctx, cache_path, prefix);
+    auto hit = ctx->tuned.find(bucket);
+    if (hit != ctx->tuned.end()) {
+        ctx->sched = hit->second;
+        return GACE_OK;
+    }
+    std::vector<gace_status> per(n);
+    auto time_it = [&](const gace_schedule& s, double& best_ms) -> gace_status {
+        ctx->sched = s;
+        double t = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            auto t0 = std::chrono::steady_clock::now();
+            gace_status st = run_requests(ctx, reqs, n, per.data(), (hipStream_t)stream, true);
+            auto t1 = std::chrono::steady_clock::now();
+            if (st != GACE_OK) return st;
+            if (rep) t = std::min(t, std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        best_ms = t;
+        return GACE_OK;
+    };
+    gace_schedule best = default_schedule();
+    double best_ms = 0;
+    if (gace_status st = time_it(best, best_ms)) return st;
+    const uint32_t wgs[] = {1, 2, 3, 4};
+    const uint32_t rows[] = {16384, 32768, 65536, 131072, 262144};
+    const uint32_t modes[] = {0, 1, 2};
+    const uint32_t caches[] = {0, 1024, 2048};
+    for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t v : wgs) {
+            gace_schedule s = best; s.wgs_per_cu = v; double ms;
+            if (time_it(s, ms) == GACE_OK && ms < best_ms) { best = s; best_ms = ms; }
+        }
+        for (uint32_t v : rows) {
+            gace_schedule s = best; s.item_rows = v; double ms;
+            if (time_it(s, ms) == GACE_OK && ms < best_ms) { best = s; best_ms = ms; }
+        }
+        for (uint32_t v : modes) {
+            gace_schedule s = best; s.count_mode = v; double ms;
+            if (time_it(s, ms) == GACE_OK && ms < best_ms) { best = s; best_ms = ms; }
+        }
+        for (uint32_t v : caches) {
+            gace_schedule s = best; s.join_cache_slots = v; double ms;
+            if (time_it(s, ms) == GACE_OK && ms < best_ms) { best = s; best_ms = ms; }
+        }
+    }
+    ctx->sched = best;
+    ctx->tuned[bucket] = best;
+    save_cache(ctx, cache_path, prefix);
+    return GACE_OK;
+}
+
+}  // extern "C"
