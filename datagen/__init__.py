@@ -415,3 +415,11 @@ def workload_bytes(w: Workload) -> int:
     tb = sum(t.n_rows * t.row_bytes for t in w.tables)
     jb = sum((j.r.n_rows + j.s.n_rows) * 8 for j in w.joins)
     return tb + jb
+
+
+def materialise(w: Workload, device="cuda"):
+    """Generate every table and join key array of a workload in device memory."""
+    tabs = [device_table(t, device) for t in w.tables]
+    keys = [(device_column(j.r.cols[0], j.r.n_rows, device), device_column(j.s.cols[0], j.s.n_rows, device))
+            for j in w.joins]
+    return tabs, keys

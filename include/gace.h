@@ -170,11 +170,12 @@ typedef struct {
 /* Launch schedule of the batched path (chosen by gace_autotune). */
 typedef struct {
     uint32_t wg_threads;       /* 256 or 512 */
-    uint32_t wgs_per_cu;       /* persistent grid = CUs * wgs_per_cu */
+    uint32_t wgs_per_cu;       /* scan kernel grid = CUs * wgs_per_cu */
     uint32_t item_rows;        /* target sampled rows per work item */
     uint32_t count_mode;       /* 0 auto, 1 ballot, 2 transpose */
-    uint32_t join_cache_slots; /* per-workgroup LDS key cache (power of two, 0 = off) */
-    uint32_t reserved[3];
+    uint32_t join_part_keys;   /* expected sampled keys per join hash partition (power of two) */
+    uint32_t join_wgs_per_cu;  /* join kernel grid = CUs * join_wgs_per_cu */
+    uint32_t reserved[2];
 } gace_schedule;
 
 /* ---------------------------------------------------------------- context */
@@ -227,6 +228,25 @@ gace_status gace_set_schedule(gace_ctx* ctx, const gace_schedule* s);
    each shared scan + 8 bytes per sampled join key). */
 gace_status gace_last_batch_stats(gace_ctx* ctx, double* kernel_ms, uint64_t* alg_bytes,
                                   uint64_t* rows_preds);
+
+/* Per-item device trace of the last batch (for profiling the batched path).
+   Item kinds: 1 scan, 2 join histogram, 3 join offsets, 4 join partition
+   starts, 5 join scatter, 6 join aggregation.  Timestamps are ticks of the
+   device's constant-rate counter (ticks_per_us of them per microsecond):
+   t_begin when a workgroup took the item, t_ready when its dependencies were
+   met, t_end when it finished.  Tracing costs one store per item. */
+typedef struct {
+    uint32_t kind;
+    uint32_t index;   /* scan or join index within the batch */
+    uint32_t wg;      /* workgroup id */
+    uint32_t xcc;     /* XCD (accelerator complex die) the workgroup ran on */
+    uint64_t t_begin, t_ready, t_end;
+    uint64_t reserved;
+} gace_trace_rec;
+
+gace_status gace_set_trace(gace_ctx* ctx, int enable);
+/* Copies up to cap records of the last batch; *n receives the total. */
+gace_status gace_get_trace(gace_ctx* ctx, gace_trace_rec* out, uint32_t cap, uint32_t* n, double* ticks_per_us);
 
 /* ---------------------------------------------------------------- serving */
 typedef struct {

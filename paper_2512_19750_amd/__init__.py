@@ -80,8 +80,14 @@ class gace_request(ctypes.Structure):
 
 class gace_schedule(ctypes.Structure):
     _fields_ = [("wg_threads", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32), ("item_rows", ctypes.c_uint32),
-                ("count_mode", ctypes.c_uint32), ("join_cache_slots", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 3)]
+                ("count_mode", ctypes.c_uint32), ("join_part_keys", ctypes.c_uint32),
+                ("join_wgs_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+
+
+class gace_trace_rec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("index", ctypes.c_uint32), ("wg", ctypes.c_uint32),
+                ("xcc", ctypes.c_uint32), ("t_begin", ctypes.c_uint64), ("t_ready", ctypes.c_uint64),
+                ("t_end", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
 
 
 class gace_server_cfg(ctypes.Structure):
@@ -98,7 +104,8 @@ class gace_server_stats(ctypes.Structure):
 ABI_FUNCTIONS = [
     "gace_create", "gace_destroy", "gace_last_error", "gace_version", "gace_check_request",
     "gace_probe_selectivity", "gace_join_freq", "gace_batch_run", "gace_autotune", "gace_get_schedule",
-    "gace_set_schedule", "gace_last_batch_stats", "gace_server_create", "gace_server_submit",
+    "gace_set_schedule", "gace_last_batch_stats", "gace_set_trace", "gace_get_trace",
+    "gace_server_create", "gace_server_submit",
     "gace_server_wait", "gace_server_stats_get", "gace_server_destroy",
 ]
 
@@ -135,6 +142,9 @@ def lib():
             "gace_set_schedule": ([P, ctypes.POINTER(gace_schedule)], i32),
             "gace_last_batch_stats": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
                                        ctypes.POINTER(u64)], i32),
+            "gace_set_trace": ([P, ctypes.c_int], i32),
+            "gace_get_trace": ([P, ctypes.POINTER(gace_trace_rec), u32, ctypes.POINTER(u32),
+                                ctypes.POINTER(ctypes.c_double)], i32),
             "gace_server_create": ([ctypes.c_int, ctypes.POINTER(gace_server_cfg), ctypes.POINTER(P)], i32),
             "gace_server_submit": ([P, ctypes.POINTER(gace_request), ctypes.POINTER(u64)], i32),
             "gace_server_wait": ([P, u64, ctypes.c_int64, ctypes.POINTER(i32)], i32),
@@ -377,7 +387,7 @@ def gace_get_schedule(ctx: int) -> dict:
     s = gace_schedule()
     _check(lib().gace_get_schedule(ctx, ctypes.byref(s)))
     return dict(wg_threads=s.wg_threads, wgs_per_cu=s.wgs_per_cu, item_rows=s.item_rows,
-                count_mode=s.count_mode, join_cache_slots=s.join_cache_slots)
+                count_mode=s.count_mode, join_part_keys=s.join_part_keys, join_wgs_per_cu=s.join_wgs_per_cu)
 
 
 def gace_set_schedule(ctx: int, **kw):
@@ -394,6 +404,23 @@ def gace_last_batch_stats(ctx: int) -> dict:
     rp = ctypes.c_uint64()
     _check(lib().gace_last_batch_stats(ctx, ctypes.byref(ms), ctypes.byref(ab), ctypes.byref(rp)))
     return dict(kernel_ms=ms.value, alg_bytes=int(ab.value), rows_preds=int(rp.value))
+
+
+def gace_set_trace(ctx: int, enable: bool = True):
+    _check(lib().gace_set_trace(ctx, 1 if enable else 0))
+
+
+def gace_get_trace(ctx: int):
+    """-> (numpy structured array of the last batch's item records, ticks per microsecond)"""
+    n = ctypes.c_uint32()
+    tpu = ctypes.c_double()
+    _check(lib().gace_get_trace(ctx, None, 0, ctypes.byref(n), ctypes.byref(tpu)))
+    recs = (gace_trace_rec * max(n.value, 1))()
+    _check(lib().gace_get_trace(ctx, recs, n.value, ctypes.byref(n), ctypes.byref(tpu)))
+    dt = np.dtype([("kind", "<u4"), ("index", "<u4"), ("wg", "<u4"), ("xcc", "<u4"), ("t_begin", "<u8"),
+                   ("t_ready", "<u8"), ("t_end", "<u8"), ("reserved", "<u8")])
+    arr = np.frombuffer(bytes(recs), dtype=dt, count=n.value).copy()
+    return arr, tpu.value
 
 
 def gace_server_create(device: int = 0, max_inflight: int = 2, max_batch: int = 256,

@@ -396,14 +396,6 @@ static uint32_t log2u(uint32_t x) {
     return l;
 }
 
-static uint64_t kept_upper(uint64_t nb, uint64_t thr) {
-    if (thr >= kThrAll) return nb;
-    const double p = (double)thr / 4294967296.0;
-    const double mu = (double)nb * p, sd = std::sqrt((double)nb * p * (1.0 - p));
-    const double hi = std::ceil(mu + 12.0 * sd + 16.0);
-    return hi >= (double)nb ? nb : (uint64_t)hi;
-}
-
 static uint64_t bpi_for(uint64_t thr, uint32_t log2B, uint32_t item_rows) {
     const double p = thr >= kThrAll ? 1.0 : (double)thr / 4294967296.0;
     if (p <= 0.0) return 0;
@@ -548,32 +540,72 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         }
     }
 
-    // ---- joins
+    // ---- joins: hash-partitioned key aggregation
     std::vector<JoinDesc> joins;
-    uint64_t sketch_bytes = 0;
+    std::vector<Item> hist_items, off_items, base_items, scatter_items, agg_items;
+    uint64_t arena_static = 0;
+    auto carve = [&](uint64_t bytes) {
+        const uint64_t off = arena_static;
+        arena_static += (bytes + 255) / 256 * 256;
+        return off;
+    };
     for (uint32_t j = 0; j < join_reqs.size(); ++j) {
         const gace_request& r = reqs[join_reqs[j]];
         JoinDesc J;
         std::memset(&J, 0, sizeof(J));
-        uint64_t U = 0;
         const gace_keys* sides[2] = {&r.R, &r.S};
-        for (int s = 0; s < 2; ++s) {
-            JoinSide& D = J.side[s];
-            D.keys = sides[s]->keys;
-            D.n = sides[s]->n;
-            D.seed = sides[s]->spec.seed;
-            D.thr = rate_threshold(sides[s]->spec.rate);
-            D.log2B = log2u(sides[s]->spec.block_rows);
+        double expect = 0.0;
+        uint32_t item = 0;
+        std::vector<Item> my_items;
+        for (uint32_t sd = 0; sd < 2; ++sd) {
+            JoinSide& D = J.side[sd];
+            D.keys = sides[sd]->keys;
+            D.n = sides[sd]->n;
+            D.seed = sides[sd]->spec.seed;
+            D.thr = rate_threshold(sides[sd]->spec.rate);
+            D.log2B = log2u(sides[sd]->spec.block_rows);
             D.n_blocks = (D.n + (1ull << D.log2B) - 1) >> D.log2B;
-            D.table_id = sides[s]->table_id;
-            U += std::min<uint64_t>(D.n, kept_upper(D.n_blocks, D.thr) << D.log2B);
+            D.table_id = sides[sd]->table_id;
+            D.item_begin = item;
+            const double p = D.thr >= kThrAll ? 1.0 : (double)D.thr / 4294967296.0;
+            expect += (double)D.n * p;
+            const uint64_t bb = bpi_for(D.thr, D.log2B, opt.item_rows);
+            if (bb && D.n)
+                for (uint64_t b = 0; b < D.n_blocks; b += bb) {
+                    Item it = {IT_JHIST, j, sd, item++, b, std::min(D.n_blocks, b + bb)};
+                    my_items.push_back(it);
+                }
+            D.n_items = item - D.item_begin;
         }
-        uint64_t cap = 2048;
-        while (cap < 2 * U) cap <<= 1;
-        J.cap_max = cap;
+        uint32_t log2P = 0;
+        while (log2P < kPartBitsMax && (double)(1u << log2P) * (double)opt.join_part_keys < expect) ++log2P;
+        const uint32_t P = 1u << log2P;
+        J.log2P = log2P;
         J.acc = j;
-        J.sketch_off = sketch_bytes;
-        out.table_bytes_max += cap * sizeof(Slot);
+        J.n_items = item;
+        J.n_off = (P + 63) / 64;
+        J.n_agg = std::min<uint32_t>(512, std::max<uint32_t>(1, (P + 15) / 16));
+        J.rows_off = carve((uint64_t)item * P * 4);
+        J.base_off = carve(2ull * (P + 1) * 4);
+        J.stats_off = carve((uint64_t)item * 16);
+        // partitions above kChunkKeys keys become chunks + a merge: at most
+        // 2 N / kChunkKeys chunks and N / kChunkKeys merges for N keys
+        const uint64_t nk = J.side[0].n + J.side[1].n;
+        const uint64_t big = nk / kChunkKeys + 1;
+        J.max_chunks = (uint32_t)std::min<uint64_t>(2 * big + 8, 0xFFFFFFF0u);
+        J.max_units = (uint32_t)std::min<uint64_t>((uint64_t)P + J.max_chunks + big + 8, 0xFFFFFFF0u);
+        J.units_off = carve((uint64_t)J.max_units * sizeof(AggUnit));
+        J.chunk_off = carve((uint64_t)J.max_chunks * 4);
+        J.done_off = carve(big * 4 + 64);
+        for (const Item& it : my_items) {
+            hist_items.push_back(it);
+            Item sc = it;
+            sc.kind = IT_JSCATTER;
+            scatter_items.push_back(sc);
+        }
+        for (uint32_t c = 0; c < J.n_off; ++c) off_items.push_back({IT_JOFF, j, 0, c, 0, 0});
+        base_items.push_back({IT_JBASE, j, 0, 0, 0, 0});
+        for (uint32_t w = 0; w < J.n_agg; ++w) agg_items.push_back({IT_JAGG, j, 0, w, 0, 0});
         joins.push_back(J);
         JoinOut jo;
         jo.req = join_reqs[j];
@@ -582,42 +614,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     }
 
     // ---- items
-    std::vector<Item> sketch_items, size_items, init_items, scan_items, build_items, final_items;
-    for (uint32_t j = 0; j < joins.size(); ++j) {
-        JoinDesc& J = joins[j];
-        uint32_t n_sketch = 0, n_build = 0;
-        for (uint32_t s = 0; s < 2; ++s) {
-            const JoinSide& D = J.side[s];
-            if (D.thr == 0 || D.n == 0) continue;
-            const double p = D.thr >= kThrAll ? 1.0 : (double)D.thr / 4294967296.0;
-            const double rows = (double)D.n * p;
-            // sketch: at most kSketchRowsPerJoin / 2 items per side
-            uint64_t want = (uint64_t)std::ceil(rows / (double)opt.item_rows);
-            if (want < 1) want = 1;
-            if (want > kSketchRowsPerJoin / 2) want = kSketchRowsPerJoin / 2;
-            uint64_t bpi = (D.n_blocks + want - 1) / want;
-            if (bpi > 64) bpi = (bpi + 63) / 64 * 64;
-            for (uint64_t b = 0; b < D.n_blocks; b += bpi) {
-                Item it = {IT_JSKETCH, j, s, n_sketch++, b, std::min(D.n_blocks, b + bpi)};
-                sketch_items.push_back(it);
-            }
-            const uint64_t bb = bpi_for(D.thr, D.log2B, opt.item_rows);
-            for (uint64_t b = 0; b < D.n_blocks; b += bb) {
-                Item it = {IT_JBUILD, j, s, 0, b, std::min(D.n_blocks, b + bb)};
-                build_items.push_back(it);
-                ++n_build;
-            }
-        }
-        J.n_sketch = n_sketch;
-        J.n_build = n_build;
-        sketch_bytes += (uint64_t)n_sketch << kHllBits;
-        size_items.push_back({IT_JSIZE, j, 0, 0, 0, 0});
-        for (uint32_t c = 0; c < kSlotChunks; ++c) {
-            init_items.push_back({IT_JINIT, j, 0, c, 0, 0});
-            final_items.push_back({IT_JFINAL, j, 0, c, 0, 0});
-        }
-        if (j + 1 < joins.size()) joins[j + 1].sketch_off = sketch_bytes;
-    }
+    std::vector<Item> scan_items;
     for (uint32_t s = 0; s < scans.size(); ++s) {
         const ScanDesc& S = scans[s];
         const uint64_t bb = bpi_for(S.thr_max, S.log2B, opt.item_rows);
@@ -631,7 +628,11 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     std::stable_sort(scan_items.begin(), scan_items.end(), [&](const Item& x, const Item& y) {
         return scans[x.idx].row_bytes * scans[x.idx].thr_max > scans[y.idx].row_bytes * scans[y.idx].thr_max;
     });
-    for (auto* v : {&sketch_items, &size_items, &init_items, &scan_items, &build_items, &final_items})
+    // scans form the first queue; the join queue follows in phase order, so a
+    // join item only ever waits for items earlier in its queue
+    out.items.insert(out.items.end(), scan_items.begin(), scan_items.end());
+    const uint32_t n_scan_items = (uint32_t)out.items.size();
+    for (auto* v : {&hist_items, &off_items, &base_items, &scatter_items, &agg_items})
         out.items.insert(out.items.end(), v->begin(), v->end());
 
     // ---- plan blob
@@ -644,6 +645,8 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     H.n_counts = n_counts;
     H.n_hist = n_hist;
     H.n_items = (uint32_t)out.items.size();
+    H.n_scan_items = n_scan_items;
+    H.arena_static = arena_static;
     std::vector<uint8_t>& blob = out.plan;
     blob.assign(sizeof(PlanHdr), 0);
     auto put = [&](const void* p, size_t nbytes) -> uint32_t {
@@ -669,7 +672,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     out.jdesc = joins;
     out.n_counts = n_counts;
     out.n_hist = n_hist;
-    out.sketch_bytes = sketch_bytes;
+    out.arena_static = arena_static;
 }
 
 }  // namespace gace

@@ -21,6 +21,7 @@ gace_status check_request(const gace_request* r, std::string& msg);
 
 struct CompileOptions {
     uint32_t item_rows = 65536;      // target sampled rows per work item
+    uint32_t join_part_keys = 1024;  // expected sampled keys per join hash partition
 };
 
 // host bookkeeping that maps plan results back to the requests
@@ -47,8 +48,7 @@ struct CompiledBatch {
     std::vector<gace_status> status; // per caller request (validation result)
     std::vector<std::string> errors;
     uint32_t n_counts = 0, n_hist = 0;
-    uint64_t sketch_bytes = 0;       // HLL rows
-    uint64_t table_bytes_max = 0;    // sum of the largest hash tables the joins may need
+    uint64_t arena_static = 0;       // joins' per-item tables at the start of the arena
 };
 
 // Validate every request; compile the valid ones.  Never throws.

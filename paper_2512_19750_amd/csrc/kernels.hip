@@ -6,12 +6,12 @@
 //            the scan (selectivity probe, Sec. III-B; Exp. D "Key-Only +
 //            Bitmask": only referenced columns are read, per-row predicate
 //            bits are reduced in registers and never stored)
-//   JSKETCH  HyperLogLog registers of the sampled join keys (sizes the table)
-//   JSIZE    table capacity from the sketch, carved from the arena
-//   JINIT    clear a slice of the join hash table
-//   JBUILD   sampled keys -> per-workgroup LDS key cache -> global open-
-//            addressing table (key-only aggregation, Sec. III-B)
-//   JFINAL   slice of the table -> NDV (Eq. 1) and sum f_R f_S
+//   JHIST    per-item hash-partition counts of the sampled join keys
+//   JOFF     per-item offsets inside each partition
+//   JBASE    partition starts; the partition buffer is carved from the arena
+//   JSCATTER sampled keys -> their hash partitions
+//   JAGG     each partition aggregated in an LDS key table -> f_R(k), f_S(k)
+//            -> NDV (Eq. 1) and sum f_R f_S (key-only aggregation, Sec. III-B)
 // Items of a join wait on the previous phase's completion counter; the host
 // orders the queue by phase, so every awaited item was popped earlier by a
 // running workgroup and the waits always end.
@@ -23,25 +23,52 @@ namespace gace {
 
 constexpr int kWG = 256;
 constexpr int kWaves = kWG / 64;
-constexpr uint32_t kScanLdsGroups = 16;          // per-item LDS counters for the first 16 groups
-constexpr uint32_t kLdsMisc = 512;
+constexpr uint32_t kScanLdsGroups = 32;          // per-item LDS counters for the first 32 groups
+constexpr uint32_t kScanLdsHist = 128;           // per-item LDS sample histogram for scans of < 128 requests
+constexpr uint32_t kLdsMisc = 768;
 constexpr uint32_t kLdsCnt = kScanLdsGroups * 64 * 4;
-constexpr uint32_t kLdsBytes = kLdsMisc + kLdsCnt + kGroupTabBudget;   // 45.5 KiB
+constexpr uint32_t kLdsHist = kScanLdsHist * 2 * 8;
+constexpr uint32_t kLdsThr = kScanLdsHist * 8 + 640;                             // thresholds + bit prefix sums
+constexpr uint32_t kLdsBytes = kLdsMisc + kLdsCnt + kLdsHist + kLdsThr + kGroupTabBudget;   // scan kernel
+constexpr uint32_t kJoinLdsBytes = kLdsMisc + 8192 * 4 + 512;                      // join kernel
+
+// explicit address spaces: pointers read from the plan are generic to the
+// compiler; global loads through them must not become flat loads, which would
+// make every LDS wait also wait for the loads in flight
+#define GACE_GLOBAL __attribute__((address_space(1)))
+#define GACE_LDS __attribute__((address_space(3)))
 
 struct BatchArgs {
     const uint8_t* plan;
     const Item* items;
-    uint32_t* head;
+    uint32_t* head;            // [0] scan queue, [1] join queue
     unsigned long long* counts;
     unsigned long long* hist;
     JoinAcc* accs;
-    uint8_t* sketch;           // HLL rows
-    uint8_t* arena_base;       // hash tables
+    uint8_t* arena_base;       // join tables and partition buffers
     Arena* arena;
     uint32_t count_mode;       // 0 auto, 1 ballot, 2 transpose
-    uint32_t cache_slots;      // join LDS key-cache slots (power of two <= 2048, 0 = off)
-    uint64_t force_cap;        // nonzero: skip the sketch estimate and use this capacity
+    uint32_t reserved;
+    TraceRec* trace;           // one record per item when the plan asks for tracing
 };
+
+// hardware register XCC_ID (s_getreg: id 20, offset 0, 4 bits): which XCD runs this wave
+__device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u; }
+
+__device__ __forceinline__ void trace_item(const BatchArgs& a, const PlanHdr& H, uint32_t idx, const Item& it,
+                                           uint64_t t0, uint64_t t1) {
+    if (!H.trace || threadIdx.x) return;
+    TraceRec r;
+    r.kind = it.kind;
+    r.index = it.idx;
+    r.wg = blockIdx.x;
+    r.xcc = xcc_id();
+    r.t_begin = t0;
+    r.t_ready = t1;
+    r.t_end = (uint64_t)wall_clock64();
+    r.reserved = 0;
+    a.trace[idx] = r;
+}
 
 // ------------------------------------------------------------------ sampler
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): word 0 of the output
@@ -70,41 +97,39 @@ __device__ __forceinline__ uint32_t key32(uint32_t v, uint32_t xf) {
     return (v & 0x80000000u) ? ~v : (v | 0x80000000u);
 }
 
-__device__ __forceinline__ uint32_t rank32(const uint32_t* bnd, uint32_t nb, uint32_t step, uint32_t k) {
+template <typename B>
+__device__ __forceinline__ uint32_t rank32(const B* bnd, uint32_t nb, uint32_t step, uint32_t k) {
     uint32_t pos = 0;
     for (; step; step >>= 1)
         if (pos + step <= nb && bnd[pos + step - 1] <= k) pos += step;
     return pos;
 }
 
-__device__ __forceinline__ uint32_t rank64(const uint64_t* bnd, uint32_t nb, uint32_t step, uint64_t k) {
+template <typename B>
+__device__ __forceinline__ uint32_t rank64(const B* bnd, uint32_t nb, uint32_t step, uint64_t k) {
     uint32_t pos = 0;
     for (; step; step >>= 1)
         if (pos + step <= nb && bnd[pos + step - 1] <= k) pos += step;
     return pos;
 }
 
-// predicate mask of row r for one group (bits of predicates whose every
-// term on these columns holds)
-__device__ __forceinline__ uint64_t eval_row(const ColProg* cp, uint32_t c0, uint32_t c1, const uint8_t* tab,
-                                             uint64_t r) {
-    uint64_t m = ~0ull;
-    for (uint32_t c = c0; c < c1; ++c) {
-        const ColProg P = cp[c];
-        uint32_t idx;
-        if (P.kind == CP_LUT32) {
-            uint32_t k = key32(__builtin_nontemporal_load((const uint32_t*)P.data + r), P.xform);
-            idx = min(max(k, P.lo), P.hi) - P.lo;
-        } else if (P.kind == CP_RANK32) {
-            uint32_t k = key32(__builtin_nontemporal_load((const uint32_t*)P.data + r), P.xform);
-            idx = rank32((const uint32_t*)(tab + P.bnd_off), P.nb, P.step, k);
-        } else {
-            uint64_t k = __builtin_nontemporal_load((const uint64_t*)P.data + r) ^ 0x8000000000000000ull;
-            idx = rank64((const uint64_t*)(tab + P.bnd_off), P.nb, P.step, k);
-        }
-        m &= ((const uint64_t*)(tab + P.mask_off))[idx];
-    }
-    return m;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+// value -> elementary-interval index of one column program; AS is the
+// address space of the group's tables (LDS when staged, else global)
+template <int AS>
+__device__ __forceinline__ uint32_t interval32(const ColProg& P, const uint8_t* tab, uint32_t v) {
+    typedef __attribute__((address_space(AS))) const uint32_t TB;
+    const uint32_t k = key32(v, P.xform);
+    if (P.kind == CP_LUT32) return min(max(k, P.lo), P.hi) - P.lo;
+    return rank32((TB*)(tab + P.bnd_off), P.nb, P.step, k);
+}
+
+template <int AS>
+__device__ __forceinline__ uint32_t interval64(const ColProg& P, const uint8_t* tab, uint64_t v) {
+    typedef __attribute__((address_space(AS))) const uint64_t TB;
+    return rank64((TB*)(tab + P.bnd_off), P.nb, P.step, v ^ 0x8000000000000000ull);
 }
 
 // ------------------------------------------------------------------ counting
@@ -151,6 +176,147 @@ __device__ __forceinline__ void count_rows(uint64_t m, uint64_t active, uint32_t
     }
 }
 
+// rows [r0, r1) of one block for one group.  The WG walks the rows in tiles
+// of 4096: wave w takes rows [tile + 1024 w, tile + 1024 (w + 1)), each lane 16
+// of them (4 quads of 4 consecutive rows, 256 rows apart).  For a 32-bit
+// column the lane issues its 4 quad loads (16 B each) at once, and the next
+// 32-bit column's loads are issued before this column's lookups, so up to 8
+// loads per lane are in flight while masks are combined.  64-bit columns are
+// loaded and looked up one quad at a time.  tab points at the group's
+// masks/boundaries in address space AS (LDS when staged, else global).
+constexpr int kQuads = 4;
+constexpr int kRows = kQuads * 4;
+
+__device__ __forceinline__ void load32(const ColProg& P, uint64_t q0, uint64_t r1, uint32_t (&v)[kRows]) {
+#pragma unroll
+    for (int j = 0; j < kQuads; ++j) {
+        const uint64_t rq = q0 + 256ull * j;
+        const int nv = rq < r1 ? (int)min((uint64_t)4, r1 - rq) : 0;
+        const GACE_GLOBAL uint32_t* p = (const GACE_GLOBAL uint32_t*)P.data + rq;
+        if (nv == 4 && (rq & 3) == 0) {
+            const u32x4 x = __builtin_nontemporal_load((const GACE_GLOBAL u32x4*)p);
+            v[4 * j + 0] = x.x; v[4 * j + 1] = x.y; v[4 * j + 2] = x.z; v[4 * j + 3] = x.w;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[4 * j + t] = t < nv ? p[t] : 0u;
+        }
+    }
+}
+
+template <int AS>
+__device__ __forceinline__ void lookup32(const ColProg& P, const uint8_t* tab, const uint32_t (&v)[kRows],
+                                         uint64_t (&m)[kRows]) {
+    typedef __attribute__((address_space(AS))) const uint64_t TM;
+    TM* masks = (TM*)(tab + P.mask_off);
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) m[i] &= masks[interval32<AS>(P, tab, v[i])];
+}
+
+template <int AS>
+__device__ __forceinline__ void lookup64(const ColProg& P, const uint8_t* tab, uint64_t q0, uint64_t r1,
+                                         uint64_t (&m)[kRows]) {
+    typedef __attribute__((address_space(AS))) const uint64_t TM;
+    TM* masks = (TM*)(tab + P.mask_off);
+#pragma unroll
+    for (int j = 0; j < kQuads; ++j) {
+        const uint64_t rq = q0 + 256ull * j;
+        const int nv = rq < r1 ? (int)min((uint64_t)4, r1 - rq) : 0;
+        const GACE_GLOBAL uint64_t* p = (const GACE_GLOBAL uint64_t*)P.data + rq;
+        uint64_t w[4] = {0, 0, 0, 0};
+        if (nv == 4 && (rq & 3) == 0) {
+            const u64x2 x = __builtin_nontemporal_load((const GACE_GLOBAL u64x2*)p);
+            const u64x2 y = __builtin_nontemporal_load((const GACE_GLOBAL u64x2*)p + 1);
+            w[0] = x.x; w[1] = x.y; w[2] = y.x; w[3] = y.y;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) w[t] = t < nv ? p[t] : 0ull;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) m[4 * j + t] &= masks[interval64<AS>(P, tab, w[t])];
+    }
+}
+
+// tiles of 4096 rows over a set of kept blocks of one 64-block chunk
+struct TileIt {
+    uint64_t start, end;        // tile start row, end row of its block
+};
+
+__device__ __forceinline__ bool tile_first(TileIt& t, unsigned long long& rest, uint64_t cb, uint64_t B,
+                                           uint64_t n) {
+    if (!rest) return false;
+    const int j = __ffsll((long long)rest) - 1;
+    rest &= rest - 1;
+    t.start = (cb + (uint64_t)j) * B;
+    t.end = t.start + B < n ? t.start + B : n;
+    return true;
+}
+
+__device__ __forceinline__ bool tile_next(TileIt& t, unsigned long long& rest, uint64_t cb, uint64_t B,
+                                          uint64_t n) {
+    t.start += (uint64_t)kWG * kRows;
+    if (t.start < t.end) return true;
+    return tile_first(t, rest, cb, B, n);
+}
+
+// all rows of the blocks in `blocks` (bit j = block cb + j) for one group.
+// The 32-bit column loads of the next column -- or of the next tile's first
+// column after the last one -- are issued before the current column's
+// lookups, so each lane keeps 4-8 loads of 16 B in flight across the whole
+// block set.  tab points at the group's masks/boundaries in address space AS
+// (LDS when staged, else global).
+template <int AS>
+__device__ __forceinline__ uint32_t scan_blocks(const ColProg* cols, uint32_t c_begin, uint32_t c_end,
+                                                const uint8_t* tab, unsigned long long blocks, uint64_t cb,
+                                                uint64_t B, uint64_t n, uint64_t active, int lane, int wave,
+                                                uint32_t mode) {
+    uint32_t cnt = 0;
+    uint32_t first32 = c_begin;
+    while (first32 < c_end && cols[first32].kind == CP_RANK64) ++first32;
+    bool any64 = false;
+    for (uint32_t c = c_begin; c < c_end; ++c) any64 |= cols[c].kind == CP_RANK64;
+    unsigned long long rest = blocks;
+    TileIt t;
+    if (!tile_first(t, rest, cb, B, n)) return 0;
+    const uint64_t lane_off = (uint64_t)wave * 256 * kQuads + 4ull * (uint64_t)lane;
+    uint32_t cur[kRows], nxt[kRows];
+    if (first32 < c_end) load32(cols[first32], t.start + lane_off, t.end, cur);
+    for (;;) {
+        const uint64_t q0 = t.start + lane_off, r1 = t.end;
+        TileIt tn = t;
+        unsigned long long rest_n = rest;
+        const bool has_next = tile_next(tn, rest_n, cb, B, n);
+        uint64_t m[kRows];
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) m[i] = active;
+        uint32_t c = first32;
+        while (c < c_end) {
+            uint32_t cn = c + 1;
+            while (cn < c_end && cols[cn].kind == CP_RANK64) ++cn;
+            if (cn < c_end) load32(cols[cn], q0, r1, nxt);
+            else if (has_next) load32(cols[first32], tn.start + lane_off, tn.end, nxt);
+            lookup32<AS>(cols[c], tab, cur, m);
+            if (cn < c_end || has_next) {
+#pragma unroll
+                for (int i = 0; i < kRows; ++i) cur[i] = nxt[i];
+            }
+            c = cn;
+        }
+        if (any64)
+            for (uint32_t c64 = c_begin; c64 < c_end; ++c64)
+                if (cols[c64].kind == CP_RANK64) lookup64<AS>(cols[c64], tab, q0, r1, m);
+#pragma unroll
+        for (int j = 0; j < kQuads; ++j) {
+            const uint64_t rq = q0 + 256ull * j;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) count_rows(rq + u < r1 ? m[4 * j + u] : 0ull, active, cnt, lane, mode);
+        }
+        if (!has_next) break;
+        t = tn;
+        rest = rest_n;
+    }
+    return cnt;
+}
+
 // wave 0 decides 64 consecutive blocks; fills s_w0[0..64) and s_keep
 __device__ __forceinline__ void decide_blocks(uint64_t cb, uint64_t b_end, uint64_t thr, uint32_t table_id,
                                               uint64_t seed, uint32_t* s_w0, unsigned long long* s_keep) {
@@ -180,12 +346,24 @@ __device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, 
     uint32_t* s_w0 = (uint32_t*)lds;
     unsigned long long* s_keep = (unsigned long long*)(lds + 256);
     int* s_staged = (int*)(lds + 264);
+    uint32_t* s_k = (uint32_t*)(lds + 384);
     uint32_t* s_cnt = (uint32_t*)(lds + kLdsMisc);
-    uint8_t* s_tab = lds + kLdsMisc + kLdsCnt;
+    unsigned long long* s_hist = (unsigned long long*)(lds + kLdsMisc + kLdsCnt);
+    uint64_t* s_thr = (uint64_t*)(lds + kLdsMisc + kLdsCnt + kLdsHist);
+    uint32_t* s_cum = (uint32_t*)(lds + kLdsMisc + kLdsCnt + kLdsHist + kScanLdsHist * 8);
+    uint8_t* s_tab = lds + kLdsMisc + kLdsCnt + kLdsHist + kLdsThr;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t n_lds_groups = S.n_groups < kScanLdsGroups ? S.n_groups : kScanLdsGroups;
+    // scans of fewer than 128 requests keep thresholds, bit prefix sums and
+    // the sample histogram in LDS for the whole item
+    const bool small = S.n_req < kScanLdsHist;
     for (uint32_t i = threadIdx.x; i < n_lds_groups * 64; i += kWG) s_cnt[i] = 0;
+    if (small) {
+        for (uint32_t i = threadIdx.x; i < 2 * (S.n_req + 1); i += kWG) s_hist[i] = 0;
+        for (uint32_t i = threadIdx.x; i < S.n_req; i += kWG) s_thr[i] = rthr[i];
+        for (uint32_t i = threadIdx.x; i <= S.n_req; i += kWG) s_cum[i] = rcum[i];
+    }
     if (threadIdx.x == 0) *s_staged = -1;
     __syncthreads();
 
@@ -193,29 +371,39 @@ __device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, 
     for (uint64_t cb = it.begin; cb < it.end; cb += 64) {
         decide_blocks(cb, it.end, S.thr_max, S.table_id, S.seed, s_w0, s_keep);
         __syncthreads();
-        unsigned long long keep = *s_keep;
-        while (keep) {
-            const int j = __ffsll((long long)keep) - 1;
-            keep &= keep - 1;
-            const uint64_t b = cb + (uint64_t)j;
-            const uint64_t w0 = s_w0[j];
-            const uint64_t r0 = b * B;
-            const uint64_t r1 = (r0 + B < S.n_rows) ? r0 + B : S.n_rows;
-            // k = number of requests whose threshold exceeds word 0 (sorted descending)
+        const unsigned long long keep = *s_keep;
+        // wave 0: k(b) = number of requests whose threshold exceeds word 0
+        // (thresholds sorted descending), and the sample histogram
+        if (threadIdx.x < 64 && ((keep >> threadIdx.x) & 1ull)) {
+            const uint64_t w0 = s_w0[threadIdx.x];
             uint32_t k = 0;
             for (uint32_t step = 1u << 31; step; step >>= 1)
-                if (k + step <= S.n_req && rthr[k + step - 1] > w0) k += step;
-            if (threadIdx.x == 0) {
-                atomicAdd(&a.hist[S.hist_off + 2 * k], (unsigned long long)(r1 - r0));
+                if (k + step <= S.n_req && (small ? s_thr[k + step - 1] : rthr[k + step - 1]) > w0) k += step;
+            s_k[threadIdx.x] = k;
+            const uint64_t r0 = (cb + threadIdx.x) * B;
+            const uint64_t rows = (r0 + B < S.n_rows ? r0 + B : S.n_rows) - r0;
+            if (small) {
+                atomicAdd(&s_hist[2 * k], (unsigned long long)rows);
+                atomicAdd(&s_hist[2 * k + 1], 1ull);
+            } else {
+                atomicAdd(&a.hist[S.hist_off + 2 * k], (unsigned long long)rows);
                 atomicAdd(&a.hist[S.hist_off + 2 * k + 1], 1ull);
             }
-            const uint32_t act_bits = rcum[k];
+        }
+        __syncthreads();
+        // blocks with the same k share their active predicates: stream them together
+        unsigned long long rest = keep;
+        while (rest) {
+            const uint32_t k0 = s_k[__ffsll((long long)rest) - 1];
+            const unsigned long long same = __ballot(((rest >> lane) & 1ull) && s_k[lane] == k0);
+            rest &= ~same;
+            const uint32_t act_bits = small ? s_cum[k0] : rcum[k0];
             for (uint32_t g = 0; g * 64 < act_bits; ++g) {
                 const GroupDesc G = groups[g];
                 const uint32_t na = act_bits - g * 64;
                 const uint64_t active = G.base_mask & (na >= 64 ? ~0ull : ((1ull << na) - 1));
                 if (active == 0) continue;
-                const uint8_t* tab = a.plan + G.tab_off;
+                uint32_t cnt;
                 if (G.tab_bytes <= kGroupTabBudget) {
                     if (*s_staged != (int)g) {
                         __syncthreads();
@@ -225,20 +413,17 @@ __device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, 
                         __syncthreads();
                         if (threadIdx.x == 0) *s_staged = (int)g;
                     }
-                    tab = s_tab;
-                }
-                uint32_t cnt = 0;
-                for (uint64_t base = r0 + (uint64_t)wave * 64; base < r1; base += kWG) {
-                    const uint64_t r = base + (uint64_t)lane;
-                    uint64_t m = 0;
-                    if (r < r1) m = eval_row(cols, G.col_begin, G.col_end, tab, r) & active;
-                    count_rows(m, active, cnt, lane, a.count_mode);
+                    cnt = scan_blocks<3>(cols, G.col_begin, G.col_end, s_tab, same, cb, B, S.n_rows, active, lane,
+                                         wave, a.count_mode);
+                } else {
+                    cnt = scan_blocks<1>(cols, G.col_begin, G.col_end, a.plan + G.tab_off, same, cb, B, S.n_rows,
+                                         active, lane, wave, a.count_mode);
                 }
                 if (cnt) {
                     if (g < n_lds_groups) atomicAdd(&s_cnt[g * 64 + lane], cnt);
                     else atomicAdd(&a.counts[slots[G.slot_index + lane]], (unsigned long long)cnt);
                 }
-                __syncthreads();   // the staged table may be replaced by the next group
+                if (S.n_groups > 1) __syncthreads();   // the staged table may be replaced by the next group
             }
         }
         __syncthreads();
@@ -248,9 +433,22 @@ __device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, 
         const uint32_t c = s_cnt[i];
         if (c) atomicAdd(&a.counts[slots[groups[i >> 6].slot_index + (i & 63)]], (unsigned long long)c);
     }
+    if (small)
+        for (uint32_t i = threadIdx.x; i < 2 * (S.n_req + 1); i += kWG) {
+            const unsigned long long v = s_hist[i];
+            if (v) atomicAdd(&a.hist[S.hist_off + i], v);
+        }
 }
 
 // ------------------------------------------------------------------ joins
+// Key-only aggregation by hash partitioning: per-item partition counts of the
+// sampled keys (JHIST) -> per-partition offsets (JOFF, JBASE) -> keys
+// scattered into their partitions (JSCATTER) -> each partition aggregated in
+// an LDS key table (JAGG), which gives f_R(k), f_S(k) for every key of the
+// partition, hence NDV and sum f_R f_S.  A partition with more distinct keys
+// than one LDS table holds is split into residue classes of the hash and
+// aggregated in several passes, so the result is exact for any input.
+
 // MurmurHash3 64-bit finalizer (Appleby, public domain): a bijection on keys
 __device__ __forceinline__ uint64_t mix_key(uint64_t k) {
     k ^= k >> 33;
@@ -261,25 +459,8 @@ __device__ __forceinline__ uint64_t mix_key(uint64_t k) {
     return k;
 }
 
-__device__ __forceinline__ bool table_add(Slot* T, uint64_t mask, uint64_t h, uint64_t key, int side, uint32_t c) {
-    uint64_t i = h & mask;
-    for (uint64_t p = 0; p <= mask; ++p) {
-        unsigned long long* kp = (unsigned long long*)&T[i].key;
-        unsigned long long k = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (k == key) {
-            atomicAdd(&T[i].cnt[side], c);
-            return true;
-        }
-        if (k == kEmptyKey) {
-            unsigned long long prev = atomicCAS(kp, (unsigned long long)kEmptyKey, (unsigned long long)key);
-            if (prev == kEmptyKey || prev == key) {
-                atomicAdd(&T[i].cnt[side], c);
-                return true;
-            }
-        }
-        i = (i + 1) & mask;
-    }
-    return false;
+__device__ __forceinline__ uint32_t part_of(uint64_t h, uint32_t log2P) {
+    return log2P ? (uint32_t)(h >> (64 - log2P)) : 0u;
 }
 
 __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, unsigned long long* s_red) {
@@ -292,183 +473,516 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, un
     return t;
 }
 
-__device__ void jsketch_item(const BatchArgs& a, const PlanHdr& H, const Item& it, uint8_t* lds) {
-    const JoinDesc J = ((const JoinDesc*)(a.plan + H.joins_off))[it.idx];
-    const JoinSide& D = J.side[it.side];
+// calls f(key) for every sampled key of blocks [b0, b1) of one side; four
+// loads per thread are issued before use
+template <typename F>
+__device__ __forceinline__ void for_each_sampled_key(const JoinSide* D, uint64_t b0, uint64_t b1, uint8_t* lds,
+                                                     F&& f) {
     uint32_t* s_w0 = (uint32_t*)lds;
     unsigned long long* s_keep = (unsigned long long*)(lds + 256);
-    uint32_t* reg = (uint32_t*)(lds + kLdsMisc);
-    const uint32_t M = 1u << kHllBits;
-    for (uint32_t i = threadIdx.x; i < M; i += kWG) reg[i] = 0;
-    __syncthreads();
-    const uint64_t B = 1ull << D.log2B;
-    for (uint64_t cb = it.begin; cb < it.end; cb += 64) {
-        decide_blocks(cb, it.end, D.thr, D.table_id, D.seed, s_w0, s_keep);
+    const uint64_t B = 1ull << D->log2B, n = D->n;
+    const GACE_GLOBAL int64_t* keys = (const GACE_GLOBAL int64_t*)D->keys;
+    for (uint64_t cb = b0; cb < b1; cb += 64) {
+        decide_blocks(cb, b1, D->thr, D->table_id, D->seed, s_w0, s_keep);
         __syncthreads();
         unsigned long long keep = *s_keep;
         while (keep) {
             const int j = __ffsll((long long)keep) - 1;
             keep &= keep - 1;
             const uint64_t r0 = (cb + (uint64_t)j) * B;
-            const uint64_t r1 = (r0 + B < D.n) ? r0 + B : D.n;
-            for (uint64_t r = r0 + threadIdx.x; r < r1; r += kWG) {
-                const uint64_t h = mix_key((uint64_t)__builtin_nontemporal_load(D.keys + r));
-                const uint32_t idx = (uint32_t)(h >> (64 - kHllBits));
-                const uint64_t w = h << kHllBits;
-                const uint32_t rho = w ? (uint32_t)__clzll((long long)w) + 1u : (uint32_t)(65 - kHllBits);
-                atomicMax(&reg[idx], rho);
-            }
-        }
-        __syncthreads();
-    }
-    uint8_t* row = a.sketch + J.sketch_off + (uint64_t)it.sub * M;
-    for (uint32_t i = threadIdx.x; i < M; i += kWG) row[i] = (uint8_t)reg[i];
-}
-
-__device__ void jsize_item(const BatchArgs& a, const PlanHdr& H, const Item& it, uint8_t* lds) {
-    const JoinDesc J = ((const JoinDesc*)(a.plan + H.joins_off))[it.idx];
-    JoinAcc& acc = a.accs[J.acc];
-    double* s_sum = (double*)(lds + kLdsMisc);
-    uint32_t* s_zero = (uint32_t*)(lds + kLdsMisc + kWG * 8);
-    const uint32_t M = 1u << kHllBits;
-    double sum = 0.0;
-    uint32_t zeros = 0;
-    for (uint32_t i = threadIdx.x; i < M; i += kWG) {
-        uint32_t mx = 0;
-        for (uint32_t s = 0; s < J.n_sketch; ++s) {
-            const uint32_t v = a.sketch[J.sketch_off + (uint64_t)s * M + i];
-            mx = v > mx ? v : mx;
-        }
-        sum += ldexp(1.0, -(int)mx);
-        zeros += mx == 0;
-    }
-    s_sum[threadIdx.x] = sum;
-    s_zero[threadIdx.x] = zeros;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        uint32_t z = 0;
-        for (int i = 0; i < kWG; ++i) { t += s_sum[i]; z += s_zero[i]; }
-        const double m = (double)M;
-        double est = (0.7213 / (1.0 + 1.079 / m)) * m * m / t;          // Flajolet et al. 2007
-        if (est <= 2.5 * m && z > 0) est = m * log(m / (double)z);       // small-range correction
-        uint64_t want = (uint64_t)(2.5 * est) + 2048;
-        uint64_t cap = 2048;
-        while (cap < want && cap < J.cap_max) cap <<= 1;
-        if (a.force_cap) cap = a.force_cap;
-        if (cap > J.cap_max) cap = J.cap_max;
-        const unsigned long long bytes = (unsigned long long)cap * sizeof(Slot);
-        const unsigned long long off = atomicAdd(&a.arena->used, bytes);
-        if (off + bytes > a.arena->size) acc.status = 2;
-        acc.table_off = off;
-        acc.cap = cap;
-    }
-}
-
-__device__ void jinit_item(const BatchArgs& a, const PlanHdr& H, const Item& it) {
-    const JoinDesc J = ((const JoinDesc*)(a.plan + H.joins_off))[it.idx];
-    JoinAcc& acc = a.accs[J.acc];
-    if (__hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    const uint64_t cap = acc.cap;
-    Slot* T = (Slot*)(a.arena_base + acc.table_off);
-    const uint64_t s0 = cap * it.sub / kSlotChunks, s1 = cap * (it.sub + 1) / kSlotChunks;
-    for (uint64_t i = s0 + threadIdx.x; i < s1; i += kWG) {
-        Slot s;
-        s.key = kEmptyKey;
-        s.cnt[0] = 0;
-        s.cnt[1] = 0;
-        T[i] = s;
-    }
-}
-
-__device__ void jbuild_item(const BatchArgs& a, const PlanHdr& H, const Item& it, uint8_t* lds) {
-    const JoinDesc J = ((const JoinDesc*)(a.plan + H.joins_off))[it.idx];
-    const JoinSide& D = J.side[it.side];
-    JoinAcc& acc = a.accs[J.acc];
-    const bool dead = __hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-    const uint64_t mask = acc.cap - 1;
-    Slot* T = (Slot*)(a.arena_base + acc.table_off);
-    const int side = (int)it.side;
-
-    uint32_t* s_w0 = (uint32_t*)lds;
-    unsigned long long* s_keep = (unsigned long long*)(lds + 256);
-    unsigned long long* s_red = (unsigned long long*)(lds + 320);
-    const uint32_t CS = a.cache_slots;
-    unsigned long long* ckey = (unsigned long long*)(lds + kLdsMisc);
-    uint32_t* ccnt = (uint32_t*)(lds + kLdsMisc + (size_t)CS * 8);
-    for (uint32_t i = threadIdx.x; i < CS; i += kWG) {
-        ckey[i] = kEmptyKey;
-        ccnt[i] = 0;
-    }
-    __syncthreads();
-
-    unsigned long long n_local = 0, sent_local = 0, fail = 0;
-    const uint64_t B = 1ull << D.log2B;
-    for (uint64_t cb = it.begin; cb < it.end; cb += 64) {
-        decide_blocks(cb, it.end, D.thr, D.table_id, D.seed, s_w0, s_keep);
-        __syncthreads();
-        unsigned long long keep = *s_keep;
-        while (keep) {
-            const int j = __ffsll((long long)keep) - 1;
-            keep &= keep - 1;
-            const uint64_t r0 = (cb + (uint64_t)j) * B;
-            const uint64_t r1 = (r0 + B < D.n) ? r0 + B : D.n;
-            for (uint64_t r = r0 + threadIdx.x; r < r1; r += kWG) {
-                const uint64_t key = (uint64_t)__builtin_nontemporal_load(D.keys + r);
-                n_local += 1;
-                if (key == kEmptyKey) { sent_local += 1; continue; }
-                if (dead) continue;
-                const uint64_t h = mix_key(key);
-                bool done = false;
-                if (CS) {
-                    uint32_t i = (uint32_t)(h >> 40) & (CS - 1);
-                    for (int p = 0; p < 8 && !done; ++p) {
-                        unsigned long long k = ckey[i];
-                        if (k == kEmptyKey) k = atomicCAS(&ckey[i], (unsigned long long)kEmptyKey, key);
-                        if (k == kEmptyKey || k == key) {
-                            atomicAdd(&ccnt[i], 1u);
-                            done = true;
-                        }
-                        i = (i + 1) & (CS - 1);
-                    }
+            const uint64_t r1 = (r0 + B < n) ? r0 + B : n;
+            for (uint64_t r = r0 + threadIdx.x; r < r1; r += 4 * kWG) {
+                uint64_t k[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint64_t rr = r + (uint64_t)u * kWG;
+                    k[u] = rr < r1 ? (uint64_t)__builtin_nontemporal_load(keys + rr) : 0ull;
                 }
-                if (!done && !table_add(T, mask, h, key, side, 1u)) fail += 1;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (r + (uint64_t)u * kWG < r1) f(k[u]);
             }
         }
         __syncthreads();
     }
-    if (!dead) {
-        for (uint32_t i = threadIdx.x; i < CS; i += kWG) {
-            const unsigned long long k = ckey[i];
-            if (k != kEmptyKey && ccnt[i] && !table_add(T, mask, mix_key(k), k, side, ccnt[i])) fail += 1;
+}
+
+__device__ void jhist_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds) {
+    const JoinSide* D = &jd->side[it.side];
+    JoinAcc& acc = a.accs[jd->acc];
+    const uint32_t log2P = jd->log2P, P = 1u << log2P;
+    unsigned long long* s_red = (unsigned long long*)(lds + 320);
+    uint32_t* cnt = (uint32_t*)(lds + kLdsMisc);
+    for (uint32_t i = threadIdx.x; i < P; i += kWG) cnt[i] = 0;
+    __syncthreads();
+    unsigned long long nall = 0, nsent = 0;
+    for_each_sampled_key(D, it.begin, it.end, lds, [&](uint64_t key) {
+        nall += 1;
+        if (key == kEmptyKey) {
+            nsent += 1;
+            return;
         }
-    }
-    const unsigned long long n = block_sum(n_local, s_red);
-    const unsigned long long sent = block_sum(sent_local, s_red);
-    const unsigned long long f = block_sum(fail, s_red);
+        atomicAdd(&cnt[part_of(mix_key(key), log2P)], 1u);
+    });
+    __syncthreads();
+    GACE_GLOBAL uint32_t* row = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off) + (uint64_t)it.sub * P;
+    for (uint32_t i = threadIdx.x; i < P; i += kWG) row[i] = cnt[i];
+    nall = block_sum(nall, s_red);
+    nsent = block_sum(nsent, s_red);
     if (threadIdx.x == 0) {
-        atomicAdd(&acc.n[side], n);
-        if (sent) atomicAdd(&acc.sent[side], sent);
-        if (f) atomicMax(&acc.status, 1ull);
+        GACE_GLOBAL unsigned long long* st = (GACE_GLOBAL unsigned long long*)(a.arena_base + jd->stats_off);
+        st[2 * it.sub] = nall;
+        st[2 * it.sub + 1] = nsent;
+    }
+    (void)acc;
+}
+
+// offsets of each item inside each partition of 64 partitions (in place:
+// a row's counts become its offsets); the partition totals go to base[]
+__device__ void joff_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds) {
+    const uint32_t P = 1u << jd->log2P;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t p = it.sub * 64 + (uint32_t)lane;
+    uint32_t* s_part = (uint32_t*)(lds + kLdsMisc);
+    GACE_GLOBAL uint32_t* rows = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off);
+    GACE_GLOBAL uint32_t* base = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off);
+    for (int s = 0; s < 2; ++s) {
+        const JoinSide* D = &jd->side[s];
+        const uint32_t ib = D->item_begin, ni = D->n_items;
+        const uint32_t q = (ni + kWaves - 1) / kWaves;
+        const uint32_t i0 = ib + min(ni, (uint32_t)wave * q), i1 = ib + min(ni, (uint32_t)(wave + 1) * q);
+        // 8 independent loads in flight per lane
+        uint32_t sum = 0;
+        if (p < P) {
+            uint32_t i = i0;
+            for (; i + 8 <= i1; i += 8) {
+                uint32_t v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = rows[(uint64_t)(i + k) * P + p];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) sum += v[k];
+            }
+            for (; i < i1; ++i) sum += rows[(uint64_t)i * P + p];
+        }
+        s_part[wave * 64 + lane] = sum;
+        __syncthreads();
+        uint32_t run = 0, total = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t v = s_part[w * 64 + lane];
+            if (w < wave) run += v;
+            total += v;
+        }
+        if (p < P) {
+            uint32_t i = i0;
+            for (; i + 8 <= i1; i += 8) {
+                uint32_t v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = rows[(uint64_t)(i + k) * P + p];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    rows[(uint64_t)(i + k) * P + p] = run;
+                    run += v[k];
+                }
+            }
+            for (; i < i1; ++i) {
+                GACE_GLOBAL uint32_t* e = &rows[(uint64_t)i * P + p];
+                const uint32_t v = *e;
+                *e = run;
+                run += v;
+            }
+            if (wave == 0) base[(uint64_t)s * (P + 1) + p] = total;
+        }
+        __syncthreads();
     }
 }
 
-__device__ void jfinal_item(const BatchArgs& a, const PlanHdr& H, const Item& it, uint8_t* lds) {
-    const JoinDesc J = ((const JoinDesc*)(a.plan + H.joins_off))[it.idx];
-    JoinAcc& acc = a.accs[J.acc];
-    unsigned long long* s_red = (unsigned long long*)(lds + 320);
-    unsigned long long jn = 0, n0 = 0, n1 = 0;
-    if (!__hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        const uint64_t cap = acc.cap;
-        const Slot* T = (const Slot*)(a.arena_base + acc.table_off);
-        const uint64_t s0 = cap * it.sub / kSlotChunks, s1 = cap * (it.sub + 1) / kSlotChunks;
-        for (uint64_t i = s0 + threadIdx.x; i < s1; i += kWG) {
-            const Slot s = T[i];
-            if (s.key != kEmptyKey) {
-                n0 += s.cnt[0] != 0;
-                n1 += s.cnt[1] != 0;
-                jn += (unsigned long long)s.cnt[0] * s.cnt[1];
+// inclusive-exclusive helper: block-wide exclusive prefix of one value per thread
+__device__ __forceinline__ unsigned long long block_excl(unsigned long long v, unsigned long long* s_loc,
+                                                         unsigned long long* total) {
+    __syncthreads();
+    s_loc[threadIdx.x] = v;
+    __syncthreads();
+    unsigned long long run = 0, all = 0;
+    for (int t = 0; t < kWG; ++t) {
+        const unsigned long long x = s_loc[t];
+        if (t < (int)threadIdx.x) run += x;
+        all += x;
+    }
+    *total = all;
+    return run;
+}
+
+__device__ __forceinline__ void put_unit(GACE_GLOBAL AggUnit* u, uint32_t part, uint32_t kind, uint32_t a,
+                                         uint32_t b, uint32_t ord) {
+    u->part = part;
+    u->kind = kind;
+    u->a = a;
+    u->b = b;
+    u->ord = ord;
+}
+
+// partition starts per side (exclusive prefix of the totals), per-side key
+// totals, the partition buffer and chunk tables carved from the arena, and
+// the list of aggregation units: partitions with more than kChunkKeys keys
+// are split into chunks followed by one merge unit
+__device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds) {
+    JoinAcc& acc = a.accs[jd->acc];
+    const uint32_t P = 1u << jd->log2P;
+    GACE_GLOBAL uint32_t* base = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off);
+    unsigned long long* s_loc = (unsigned long long*)(lds + kLdsMisc);
+    const uint32_t chunk = (P + kWG - 1) / kWG;
+    const uint32_t lo = min(P, threadIdx.x * chunk), hi = min(P, lo + chunk);
+    unsigned long long tot[2];
+    for (int s = 0; s < 2; ++s) {
+        GACE_GLOBAL uint32_t* b = base + (uint64_t)s * (P + 1);
+        unsigned long long local = 0;
+        for (uint32_t i = lo; i < hi; ++i) local += b[i];
+        unsigned long long run = block_excl(local, s_loc, &tot[s]);
+        for (uint32_t i = lo; i < hi; ++i) {
+            const uint32_t v = b[i];
+            b[i] = (uint32_t)run;
+            run += v;
+        }
+        if (threadIdx.x == 0) b[P] = (uint32_t)tot[s];
+    }
+    __syncthreads();
+    // aggregation units
+    const GACE_GLOBAL uint32_t* b0 = base;
+    const GACE_GLOBAL uint32_t* b1 = base + (P + 1);
+    unsigned long long n_chunk = 0, n_small = 0, n_split = 0;
+    for (uint32_t p = lo; p < hi; ++p) {
+        const uint64_t np = (uint64_t)(b0[p + 1] - b0[p]) + (b1[p + 1] - b1[p]);
+        if (np > kChunkKeys) {
+            n_chunk += (np + kChunkKeys - 1) / kChunkKeys;
+            n_split += 1;
+        } else if (np) {
+            n_small += 1;
+        }
+    }
+    unsigned long long t_chunk, t_small, t_split;
+    unsigned long long c_at = block_excl(n_chunk, s_loc, &t_chunk);
+    unsigned long long s_at = block_excl(n_small, s_loc, &t_small) + t_chunk;
+    unsigned long long m_ord = block_excl(n_split, s_loc, &t_split);
+    GACE_GLOBAL AggUnit* units = (GACE_GLOBAL AggUnit*)(a.arena_base + jd->units_off);
+    GACE_GLOBAL uint32_t* done = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->done_off);
+    const bool fits = t_chunk <= jd->max_chunks && t_chunk + t_small + t_split <= jd->max_units;
+    if (fits) {
+        for (uint32_t p = lo; p < hi; ++p) {
+            const uint64_t np = (uint64_t)(b0[p + 1] - b0[p]) + (b1[p + 1] - b1[p]);
+            if (np > kChunkKeys) {
+                const uint32_t nc = (uint32_t)((np + kChunkKeys - 1) / kChunkKeys);
+                for (uint32_t c = 0; c < nc; ++c)
+                    put_unit(units + c_at + c, p, AU_CHUNK, c, (uint32_t)(c_at + c), (uint32_t)m_ord);
+                put_unit(units + t_chunk + t_small + m_ord, p, AU_MERGE, (uint32_t)c_at, nc, (uint32_t)m_ord);
+                done[m_ord] = 0;
+                c_at += nc;
+                m_ord += 1;
+            } else if (np) {
+                put_unit(units + s_at, p, AU_SMALL, 0, 0, 0);
+                ++s_at;
             }
+        }
+    }
+    // per-side sampled and sentinel key counts from the histogram items
+    {
+        const GACE_GLOBAL unsigned long long* st =
+            (const GACE_GLOBAL unsigned long long*)(a.arena_base + jd->stats_off);
+        unsigned long long v[4] = {0, 0, 0, 0};
+        for (int sd = 0; sd < 2; ++sd)
+            for (uint32_t i = jd->side[sd].item_begin + threadIdx.x;
+                 i < jd->side[sd].item_begin + jd->side[sd].n_items; i += kWG) {
+                v[2 * sd] += st[2 * i];
+                v[2 * sd + 1] += st[2 * i + 1];
+            }
+        unsigned long long* s_red = (unsigned long long*)(lds + 320);
+        for (int k = 0; k < 4; ++k) v[k] = block_sum(v[k], s_red);
+        if (threadIdx.x == 0) {
+            acc.n[0] = v[0];
+            acc.sent[0] = v[1];
+            acc.n[1] = v[2];
+            acc.sent[1] = v[3];
+        }
+    }
+    if (threadIdx.x == 0) {
+        acc.nkeys[0] = tot[0];
+        acc.nkeys[1] = tot[1];
+        acc.n_units = (uint32_t)(t_chunk + t_small + t_split);
+        const unsigned long long kbytes = 8ull * (tot[0] + tot[1]);
+        const unsigned long long mbytes = t_chunk * (unsigned long long)kChunkKeys * sizeof(MergeEntry);
+        const unsigned long long off = atomicAdd(&a.arena->used, kbytes + mbytes);
+        if (!fits || off + kbytes + mbytes > a.arena->size) acc.status = 2;
+        acc.buf_off = off;
+        acc.merge_off = off + kbytes;
+    }
+}
+
+__device__ void jscatter_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds) {
+    JoinAcc& acc = a.accs[jd->acc];
+    const uint32_t log2P = jd->log2P, P = 1u << log2P;
+    const GACE_GLOBAL uint32_t* base =
+        (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off) + (uint64_t)it.side * (P + 1);
+    const GACE_GLOBAL uint32_t* row = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off) + (uint64_t)it.sub * P;
+    uint32_t* cur = (uint32_t*)(lds + kLdsMisc);
+    for (uint32_t i = threadIdx.x; i < P; i += kWG) cur[i] = base[i] + row[i];
+    __syncthreads();
+    if (__hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    GACE_GLOBAL int64_t* buf = (GACE_GLOBAL int64_t*)(a.arena_base + acc.buf_off) + (it.side ? acc.nkeys[0] : 0ull);
+    for_each_sampled_key(&jd->side[it.side], it.begin, it.end, lds, [&](uint64_t key) {
+        if (key == kEmptyKey) return;
+        const uint32_t pos = atomicAdd(&cur[part_of(mix_key(key), log2P)], 1u);
+        buf[pos] = (int64_t)key;
+    });
+}
+
+// LDS table of one aggregation pass
+struct AggLds {
+    unsigned long long* key;
+    uint32_t* c0;
+    uint32_t* c1;
+};
+
+__device__ __forceinline__ void agg_insert(AggLds& T, uint64_t h, uint64_t key, uint32_t c0, uint32_t c1,
+                                           uint32_t* s_claims, uint32_t* s_over) {
+    uint32_t i = (uint32_t)(h >> 20) & (kAggSlots - 1);
+    for (uint32_t probe = 0; probe < kAggSlots; ++probe) {
+        unsigned long long k = T.key[i];
+        if (k == kEmptyKey) {
+            if (atomicAdd(s_claims, 1u) >= kAggLimit) {
+                *s_over = 1;
+                return;
+            }
+            k = atomicCAS(&T.key[i], (unsigned long long)kEmptyKey, (unsigned long long)key);
+            if (k == kEmptyKey) k = key;
+        }
+        if (k == key) {
+            if (c0) atomicAdd(&T.c0[i], c0);
+            if (c1) atomicAdd(&T.c1[i], c1);
+            return;
+        }
+        i = (i + 1) & (kAggSlots - 1);
+    }
+    *s_over = 1;
+}
+
+// one segment of aggregation input: either bare keys of one side (count 1)
+// or chunk-table entries carrying both counts
+struct AggSeg {
+    const GACE_GLOBAL int64_t* keys;        // bare keys, or nullptr
+    const GACE_GLOBAL MergeEntry* ent;      // chunk-table entries, or nullptr
+    uint64_t n;
+    int side;
+};
+
+// insert the segment's entries whose hash lies in residue class res mod m;
+// the first valid lane's key absorbs its duplicates in the wave (Zipf heads)
+__device__ __forceinline__ void agg_segment(AggLds& T, const AggSeg& sg, uint64_t m, uint64_t res, uint32_t* s_ctl) {
+    const int lane = threadIdx.x & 63;
+    for (uint64_t e = threadIdx.x; e - threadIdx.x < sg.n; e += kWG) {
+        const bool inr = e < sg.n;
+        uint64_t key = 0;
+        uint32_t c0 = 0, c1 = 0;
+        if (inr) {
+            if (sg.keys) {
+                key = (uint64_t)sg.keys[e];
+                c0 = sg.side == 0;
+                c1 = sg.side == 1;
+            } else {
+                key = sg.ent[e].key;
+                c0 = sg.ent[e].c0;
+                c1 = sg.ent[e].c1;
+            }
+        }
+        const uint64_t h = mix_key(key);
+        const bool valid = inr && (h & (m - 1)) == res &&
+                           !__hip_atomic_load(&s_ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const unsigned long long vb = __ballot(valid);
+        if (!vb) continue;
+        const int lead = __ffsll((long long)vb) - 1;
+        const uint64_t klead = __shfl(key, lead);
+        const unsigned long long eq = __ballot(valid && key == klead);
+        bool go = valid;
+        const int ne = __popcll(eq);
+        if (ne > 1) {
+            const bool mine = (eq >> lane) & 1ull;
+            uint32_t s0, s1;
+            if (sg.keys) {
+                s0 = sg.side == 0 ? (uint32_t)ne : 0u;
+                s1 = sg.side == 1 ? (uint32_t)ne : 0u;
+            } else {
+                s0 = mine ? c0 : 0u;
+                s1 = mine ? c1 : 0u;
+                for (int o = 32; o; o >>= 1) {
+                    s0 += __shfl_xor(s0, o);
+                    s1 += __shfl_xor(s1, o);
+                }
+            }
+            if (mine) {
+                go = lane == lead;
+                c0 = s0;
+                c1 = s1;
+            }
+        }
+        if (go) agg_insert(T, h, key, c0, c1, &s_ctl[0], &s_ctl[1]);
+    }
+}
+
+// aggregate the segments exactly: residue classes of the hash are split until
+// each class's distinct keys fit one LDS table.  emit == nullptr: add NDV and
+// join partials to n0, n1, jn; else write each table entry to emit (count in
+// *s_emit).
+template <typename SegAt>
+__device__ void aggregate(AggLds& T, uint32_t nseg, SegAt&& seg_at, uint32_t* s_ctl, uint32_t* stack,
+                          GACE_GLOBAL MergeEntry* emit, unsigned long long& n0, unsigned long long& n1,
+                          unsigned long long& jn, JoinAcc& acc) {
+    if (threadIdx.x == 0) {
+        stack[0] = 1;
+        stack[1] = 0;
+        s_ctl[3] = 1;
+        s_ctl[6] = 0;
+    }
+    __syncthreads();
+    while (s_ctl[3] > 0) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t sp = s_ctl[3] - 1;
+            s_ctl[4] = stack[2 * sp];
+            s_ctl[5] = stack[2 * sp + 1];
+            s_ctl[3] = sp;
+            s_ctl[0] = 0;
+            s_ctl[1] = 0;
+        }
+        for (uint32_t i = threadIdx.x; i < kAggSlots; i += kWG) {
+            T.key[i] = kEmptyKey;
+            T.c0[i] = 0;
+            T.c1[i] = 0;
+        }
+        __syncthreads();
+        const uint64_t m = s_ctl[4], res = s_ctl[5];
+        for (uint32_t g = 0; g < nseg; ++g) agg_segment(T, seg_at(g), m, res, s_ctl);
+        __syncthreads();
+        if (s_ctl[1]) {
+            if (threadIdx.x == 0) {
+                const uint32_t sp = s_ctl[3];
+                if (m < (1u << 20) && sp + 2 <= 64) {
+                    stack[2 * sp] = 2 * (uint32_t)m;
+                    stack[2 * sp + 1] = (uint32_t)res;
+                    stack[2 * sp + 2] = 2 * (uint32_t)m;
+                    stack[2 * sp + 3] = (uint32_t)(res + m);
+                    s_ctl[3] = sp + 2;
+                } else {
+                    atomicMax(&acc.status, 3ull);
+                    s_ctl[3] = 0;
+                }
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < kAggSlots; i += kWG) {
+                const unsigned long long k = T.key[i];
+                if (k == kEmptyKey) continue;
+                const uint32_t x = T.c0[i], y = T.c1[i];
+                if (emit) {
+                    const uint32_t at = atomicAdd(&s_ctl[6], 1u);
+                    emit[at].key = k;
+                    emit[at].c0 = x;
+                    emit[at].c1 = y;
+                } else {
+                    n0 += x != 0;
+                    n1 += y != 0;
+                    jn += (unsigned long long)x * y;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds) {
+    JoinAcc& acc = a.accs[jd->acc];
+    const uint32_t P = 1u << jd->log2P;
+    unsigned long long* s_red = (unsigned long long*)(lds + 320);
+    uint32_t* s_ctl = (uint32_t*)(lds + 352);   // [0] claims [1] over [2] unit [3] sp [4] m [5] r [6] emitted
+    AggLds T;
+    T.key = (unsigned long long*)(lds + kLdsMisc);
+    T.c0 = (uint32_t*)(lds + kLdsMisc + kAggSlots * 8);
+    T.c1 = (uint32_t*)(lds + kLdsMisc + kAggSlots * 12);
+    uint32_t* stack = (uint32_t*)(lds + kLdsMisc + kAggSlots * 16);   // 64 x (m, r)
+    const GACE_GLOBAL uint32_t* base0 = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off);
+    const GACE_GLOBAL uint32_t* base1 = base0 + (P + 1);
+    const GACE_GLOBAL AggUnit* units = (const GACE_GLOBAL AggUnit*)(a.arena_base + jd->units_off);
+    GACE_GLOBAL uint32_t* chunk_cnt = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->chunk_off);
+    uint32_t* done = (uint32_t*)(a.arena_base + jd->done_off);
+    unsigned long long jn = 0, n0 = 0, n1 = 0;
+    const bool dead = __hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    const GACE_GLOBAL int64_t* bufR = (const GACE_GLOBAL int64_t*)(a.arena_base + acc.buf_off);
+    const GACE_GLOBAL int64_t* bufS = bufR + acc.nkeys[0];
+    GACE_GLOBAL MergeEntry* merge = (GACE_GLOBAL MergeEntry*)(a.arena_base + acc.merge_off);
+    const uint32_t n_units = acc.n_units;
+    while (!dead) {
+        if (threadIdx.x == 0) s_ctl[2] = atomicAdd(&acc.next_unit, 1u);
+        __syncthreads();
+        const uint32_t u = s_ctl[2];
+        __syncthreads();
+        if (u >= n_units) break;
+        AggUnit U;
+        U.part = units[u].part;
+        U.kind = units[u].kind;
+        U.a = units[u].a;
+        U.b = units[u].b;
+        U.ord = units[u].ord;
+        const uint32_t p = U.part;
+        const uint64_t bR = base0[p], nR = base0[p + 1] - bR, bS = base1[p], nS = base1[p + 1] - bS;
+        if (U.kind == AU_MERGE) {
+            // wait until every chunk of this partition has emitted its table
+            if (threadIdx.x == 0) {
+                while (__hip_atomic_load(&done[U.ord], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < U.b)
+                    __builtin_amdgcn_s_sleep(2);
+            }
+            __syncthreads();
+            __threadfence();
+            aggregate(
+                T, U.b,
+                [&](uint32_t c) {
+                    AggSeg sg;
+                    sg.keys = nullptr;
+                    sg.ent = merge + (uint64_t)(U.a + c) * kChunkKeys;
+                    sg.n = chunk_cnt[U.a + c];
+                    sg.side = 0;
+                    return sg;
+                },
+                s_ctl, stack, nullptr, n0, n1, jn, acc);
+            continue;
+        }
+        uint64_t lo = 0, hi = nR + nS;
+        if (U.kind == AU_CHUNK) {
+            lo = (uint64_t)U.a * kChunkKeys;
+            hi = min(hi, lo + kChunkKeys);
+        }
+        // the unit's keys: [lo, hi) of the partition's R keys followed by its S keys
+        auto seg_at = [&](uint32_t g) {
+            AggSeg sg;
+            sg.ent = nullptr;
+            const bool has_r = lo < nR;
+            if (g == 0 && has_r) {
+                sg.keys = bufR + bR + lo;
+                sg.n = min(hi, nR) - lo;
+                sg.side = 0;
+            } else {
+                const uint64_t s0 = lo > nR ? lo - nR : 0;
+                sg.keys = bufS + bS + s0;
+                sg.n = hi > nR ? (hi - nR) - s0 : 0;
+                sg.side = 1;
+            }
+            return sg;
+        };
+        const uint32_t nseg = (lo < nR ? 1u : 0u) + (hi > nR ? 1u : 0u);
+        if (U.kind == AU_CHUNK) {
+            aggregate(T, nseg, seg_at, s_ctl, stack, merge + (uint64_t)U.b * kChunkKeys, n0, n1, jn, acc);
+            if (threadIdx.x == 0) {
+                chunk_cnt[U.b] = s_ctl[6];
+                __threadfence();
+                atomicAdd(&done[U.ord], 1u);
+            }
+        } else {
+            aggregate(T, nseg, seg_at, s_ctl, stack, nullptr, n0, n1, jn, acc);
         }
     }
     jn = block_sum(jn, s_red);
@@ -479,8 +993,8 @@ __device__ void jfinal_item(const BatchArgs& a, const PlanHdr& H, const Item& it
         if (n0) atomicAdd(&acc.ndv[0], n0);
         if (n1) atomicAdd(&acc.ndv[1], n1);
         __threadfence();
-        if (atomicAdd(&acc.final_done, 1u) == kSlotChunks - 1) {
-            // last slice: the sentinel key, counted outside the table
+        if (atomicAdd(&acc.agg_done, 1u) == jd->n_agg - 1) {
+            // last worker: the sentinel key, counted outside the tables
             __threadfence();
             const unsigned long long s0 = atomicAdd(&acc.sent[0], 0ull), s1 = atomicAdd(&acc.sent[1], 0ull);
             if (s0 && s1) atomicAdd(&acc.join, s0 * s1);
@@ -508,52 +1022,77 @@ __device__ __forceinline__ void signal_count(uint32_t* p) {
     }
 }
 
-__global__ void __launch_bounds__(kWG) gace_batch_kernel(BatchArgs a) {
+// pop the next item of one queue (items [first, last) of the plan's list)
+__device__ __forceinline__ uint32_t pop_item(uint32_t* head, uint32_t first, uint32_t* s_item) {
+    if (threadIdx.x == 0) *s_item = first + atomicAdd(head, 1u);
+    __syncthreads();
+    const uint32_t idx = *s_item;
+    __syncthreads();
+    return idx;
+}
+
+// selectivity scans (queue 0: items [0, n_scan_items))
+__global__ void __launch_bounds__(kWG) gace_scan_kernel(BatchArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ uint32_t s_item;
     const PlanHdr H = *(const PlanHdr*)a.plan;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(a.head, 1u);
-        __syncthreads();
-        const uint32_t idx = s_item;
-        __syncthreads();
-        if (idx >= H.n_items) break;
+        const uint32_t idx = pop_item(&a.head[0], 0, &s_item);
+        if (idx >= H.n_scan_items) break;
+        const uint64_t t0 = (uint64_t)wall_clock64();
         const Item it = a.items[idx];
-        if (it.kind == IT_SCAN) {
-            scan_item(a, H, it, lds);
-            __syncthreads();
-            continue;
-        }
+        scan_item(a, H, it, lds);
+        __syncthreads();
+        trace_item(a, H, idx, it, t0, t0);
+    }
+}
+
+// join phases (queue 1: items [n_scan_items, n_items), in phase order)
+__global__ void __launch_bounds__(kWG) gace_join_kernel(BatchArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    __shared__ uint32_t s_item;
+    const PlanHdr H = *(const PlanHdr*)a.plan;
+    for (;;) {
+        const uint32_t idx = pop_item(&a.head[1], H.n_scan_items, &s_item);
+        if (idx >= H.n_items) break;
+        const uint64_t t0 = (uint64_t)wall_clock64();
+        uint64_t t1 = t0;
+        const Item it = a.items[idx];
         const JoinDesc* jd = (const JoinDesc*)(a.plan + H.joins_off) + it.idx;
         JoinAcc& acc = a.accs[jd->acc];
         switch (it.kind) {
-            case IT_JSKETCH:
-                jsketch_item(a, H, it, lds);
-                signal_count(&acc.sketch_done);
+            case IT_JHIST:
+                jhist_item(a, jd, it, lds);
+                signal_count(&acc.hist_done);
                 break;
-            case IT_JSIZE:
-                wait_count(&acc.sketch_done, jd->n_sketch);
-                jsize_item(a, H, it, lds);
-                signal_count(&acc.size_done);
+            case IT_JOFF:
+                wait_count(&acc.hist_done, jd->n_items);
+                t1 = (uint64_t)wall_clock64();
+                joff_item(a, jd, it, lds);
+                signal_count(&acc.off_done);
                 break;
-            case IT_JINIT:
-                wait_count(&acc.size_done, 1);
-                jinit_item(a, H, it);
-                signal_count(&acc.init_done);
+            case IT_JBASE:
+                wait_count(&acc.off_done, jd->n_off);
+                t1 = (uint64_t)wall_clock64();
+                jbase_item(a, jd, lds);
+                signal_count(&acc.base_done);
                 break;
-            case IT_JBUILD:
-                wait_count(&acc.init_done, kSlotChunks);
-                jbuild_item(a, H, it, lds);
-                signal_count(&acc.build_done);
+            case IT_JSCATTER:
+                wait_count(&acc.base_done, 1);
+                t1 = (uint64_t)wall_clock64();
+                jscatter_item(a, jd, it, lds);
+                signal_count(&acc.scatter_done);
                 break;
-            case IT_JFINAL:
-                wait_count(&acc.build_done, jd->n_build);
-                jfinal_item(a, H, it, lds);
+            case IT_JAGG:
+                wait_count(&acc.scatter_done, jd->n_items);
+                t1 = (uint64_t)wall_clock64();
+                jagg_item(a, jd, it, lds);
                 break;
             default:
                 break;
         }
         __syncthreads();
+        trace_item(a, H, idx, it, t0, t1);
     }
 }
 
@@ -570,8 +1109,9 @@ __global__ void __launch_bounds__(kWG) gace_init_kernel(const uint8_t* plan, uin
     const uint64_t nacc = (uint64_t)H.n_joins * (sizeof(JoinAcc) / 8);
     for (uint64_t i = tid; i < nacc; i += stride) ((unsigned long long*)accs)[i] = 0;
     if (tid == 0) {
-        *head = 0;
-        arena->used = 0;
+        head[0] = 0;
+        head[1] = 0;
+        arena->used = H.arena_static;
     }
 }
 
@@ -588,13 +1128,16 @@ hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hi
     return hipGetLastError();
 }
 
-hipError_t gace_launch_batch(const void* args, uint32_t grid, hipStream_t stream) {
+hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream) {
     const gace::BatchArgs& a = *(const gace::BatchArgs*)args;
-    hipLaunchKernelGGL(gace::gace_batch_kernel, dim3(grid), dim3(gace::kWG), gace::kLdsBytes, stream, a);
+    hipLaunchKernelGGL(gace::gace_scan_kernel, dim3(grid), dim3(gace::kWG), gace::kLdsBytes, stream, a);
     return hipGetLastError();
 }
 
-uint32_t gace_batch_lds_bytes(void) { return gace::kLdsBytes; }
-uint32_t gace_batch_wg_threads(void) { return gace::kWG; }
+hipError_t gace_launch_join(const void* args, uint32_t grid, hipStream_t stream) {
+    const gace::BatchArgs& a = *(const gace::BatchArgs*)args;
+    hipLaunchKernelGGL(gace::gace_join_kernel, dim3(grid), dim3(gace::kWG), gace::kJoinLdsBytes, stream, a);
+    return hipGetLastError();
+}
 
 }

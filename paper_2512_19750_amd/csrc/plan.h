@@ -18,10 +18,11 @@ constexpr uint32_t kMaxPredsPerReq = 65536;
 constexpr uint64_t kThrAll = 1ull << 32;               // threshold meaning "keep every block"
 constexpr uint32_t kLutMaxEntries = 2048;              // LUT programs up to this many entries
 constexpr uint32_t kGroupTabBudget = 40u << 10;        // group tables staged in LDS up to this size
-constexpr uint64_t kEmptyKey = 0x8000000000000000ull;  // hash-table sentinel (INT64_MIN), counted out of band
-constexpr uint32_t kHllBits = 12;                      // 4096 HyperLogLog registers (table sizing only)
-constexpr uint32_t kSketchRowsPerJoin = 64;            // max sketch items per join
-constexpr uint32_t kSlotChunks = 64;                   // init / final items per join
+constexpr uint64_t kEmptyKey = 0x8000000000000000ull;  // LDS table sentinel (INT64_MIN), counted out of band
+constexpr uint32_t kPartBitsMax = 13;                  // at most 8192 hash partitions per join
+constexpr uint32_t kAggSlots = 2048;                   // LDS key-table slots of one aggregation pass
+constexpr uint32_t kAggLimit = 1536;                   // distinct keys one pass may claim (load 0.75)
+constexpr uint32_t kChunkKeys = 1u << 17;              // a partition with more keys is split into chunks + merge
 
 // column program kinds
 enum : uint32_t { CP_LUT32 = 1, CP_RANK32 = 2, CP_RANK64 = 3 };
@@ -32,7 +33,17 @@ struct PlanHdr {
     uint32_t n_scans, n_groups, n_cols, n_joins;
     uint32_t scans_off, groups_off, cols_off, slots_off;   // byte offsets from the plan base
     uint32_t reqthr_off, reqcum_off, joins_off, total_bytes;
-    uint32_t n_counts, n_hist, n_items, reserved;
+    uint32_t n_counts, n_hist, n_items, n_scan_items;   // items [0, n_scan_items) are scans
+    uint64_t arena_static;   // bytes of the arena holding the joins' per-item tables
+    uint32_t trace;          // nonzero: kernels write one TraceRec per item
+    uint32_t reserved2;
+};
+
+// per-item trace record (same layout as gace_trace_rec)
+struct TraceRec {
+    uint32_t kind, index, wg, xcc;
+    uint64_t t_begin, t_ready, t_end;   // steady-counter ticks: popped, dependencies met, done
+    uint64_t reserved;
 };
 
 // one shared pass over one table's kept blocks
@@ -78,43 +89,67 @@ struct JoinSide {
     uint64_t thr;
     uint64_t n_blocks;
     uint32_t table_id, log2B;
+    uint32_t item_begin, n_items;   // this side's rows in the join's per-item tables
 };
 
 struct JoinDesc {
     JoinSide side[2];        // 0 = R, 1 = S
-    uint64_t cap_max;        // slot cap the sampled-key bound allows (power of two)
     uint32_t acc;            // index of this join's JoinAcc
-    uint32_t n_sketch, n_build, reserved;
-    uint64_t sketch_off;     // byte offset of n_sketch x 4096 u8 HLL rows in the join workspace
+    uint32_t log2P;          // hash partitions: P = 2^log2P (top bits of the key hash)
+    uint32_t n_items;        // histogram / scatter items (R then S)
+    uint32_t n_off;          // offset items (64 partitions each)
+    uint32_t n_agg;          // aggregation workers
+    uint32_t reserved;
+    uint64_t rows_off;       // arena offset: per-item partition counts, then offsets, [n_items][P] u32
+    uint64_t base_off;       // arena offset: [2][P + 1] u32 partition starts per side
+    uint64_t stats_off;      // arena offset: per item {sampled keys, sentinel keys} u64
+    uint64_t units_off;      // arena offset: aggregation units (AggUnit), capacity max_units
+    uint64_t chunk_off;      // arena offset: per chunk slot, u32 entries emitted
+    uint64_t done_off;       // arena offset: per split partition, u32 finished chunks
+    uint32_t max_units, max_chunks;
 };
 
-// hash-table slot: key + per-side counts
-struct Slot {
+// aggregation work unit: a whole partition, one chunk of a split partition, or
+// the merge of a split partition's chunk tables
+enum : uint32_t { AU_SMALL = 0, AU_CHUNK = 1, AU_MERGE = 2 };
+struct AggUnit {
+    uint32_t part;
+    uint32_t kind;
+    uint32_t a;              // CHUNK: chunk index in the partition; MERGE: first chunk slot
+    uint32_t b;              // CHUNK: chunk slot; MERGE: number of chunks
+    uint32_t ord;            // CHUNK / MERGE: split-partition ordinal (done counter)
+    uint32_t reserved[3];
+};
+
+// entry of a chunk table handed to the merge
+struct MergeEntry {
     uint64_t key;
-    uint32_t cnt[2];
+    uint32_t c0, c1;
 };
 
 // per-join device accumulators and phase counters (zeroed before each batch)
 struct JoinAcc {
     unsigned long long join, ndv[2], n[2], sent[2];
-    unsigned long long table_off, cap;      // chosen after the sketch phase
-    unsigned long long status;              // 0 ok, 1 table full (rerun), 2 arena exhausted
-    uint32_t sketch_done, size_done, init_done, build_done;
-    uint32_t final_done, reserved[3];
+    unsigned long long buf_off;             // arena offset of the partitioned keys (R then S)
+    unsigned long long nkeys[2];            // sampled keys per side other than the sentinel value
+    unsigned long long status;              // 0 ok, 2 arena exhausted, 3 aggregation stack overflow
+    unsigned long long merge_off;           // arena offset of the chunk tables (kChunkKeys entries per slot)
+    uint32_t next_unit, n_units;
+    uint32_t hist_done, off_done, base_done, scatter_done, agg_done, reserved;
 };
 
-struct Arena {                              // bump allocator for hash tables
+struct Arena {                              // bump allocator for partition buffers
     unsigned long long used, size;
 };
 
 // work item of the persistent batch kernel
-enum : uint32_t { IT_SCAN = 1, IT_JSKETCH = 2, IT_JSIZE = 3, IT_JINIT = 4, IT_JBUILD = 5, IT_JFINAL = 6 };
+enum : uint32_t { IT_SCAN = 1, IT_JHIST = 2, IT_JOFF = 3, IT_JBASE = 4, IT_JSCATTER = 5, IT_JAGG = 6 };
 struct Item {
     uint32_t kind;
     uint32_t idx;            // scan or join index
-    uint32_t side;           // JSKETCH / JBUILD: 0 = R, 1 = S
-    uint32_t sub;            // JSKETCH: sketch row; JINIT / JFINAL: chunk
-    uint64_t begin, end;     // block range (SCAN, JSKETCH, JBUILD)
+    uint32_t side;           // JHIST / JSCATTER: 0 = R, 1 = S
+    uint32_t sub;            // JHIST / JSCATTER: item row; JOFF: 64-partition chunk; JAGG: worker
+    uint64_t begin, end;     // block range (SCAN, JHIST, JSCATTER)
 };
 
 }  // namespace gace

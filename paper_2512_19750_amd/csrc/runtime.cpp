@@ -15,8 +15,8 @@
 extern "C" {
 hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,
                             hipStream_t stream);
-hipError_t gace_launch_batch(const void* args, uint32_t grid, hipStream_t stream);
-uint32_t gace_batch_lds_bytes(void);
+hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream);
+hipError_t gace_launch_join(const void* args, uint32_t grid, hipStream_t stream);
 }
 
 namespace gace {
@@ -29,12 +29,11 @@ struct BatchArgsHost {
     unsigned long long* counts;
     unsigned long long* hist;
     JoinAcc* accs;
-    uint8_t* sketch;
     uint8_t* arena_base;
     Arena* arena;
     uint32_t count_mode;
-    uint32_t cache_slots;
-    uint64_t force_cap;
+    uint32_t reserved;
+    TraceRec* trace;
 };
 
 static thread_local std::string g_err;
@@ -56,19 +55,21 @@ static gace_schedule default_schedule() {
     std::memset(&s, 0, sizeof(s));
     s.wg_threads = 256;
     s.wgs_per_cu = 2;
-    s.item_rows = 65536;
+    s.item_rows = 131072;
     s.count_mode = 0;
-    s.join_cache_slots = 2048;
+    s.join_part_keys = 1024;
+    s.join_wgs_per_cu = 4;
     return s;
 }
 
 static bool valid_schedule(const gace_schedule& s) {
-    const uint32_t cs = s.join_cache_slots;
-    return s.wg_threads == 256 && s.wgs_per_cu >= 1 && s.wgs_per_cu <= 8 && s.item_rows >= 1024 &&
-           s.count_mode <= 2 && (cs == 0 || (cs <= 2048 && (cs & (cs - 1)) == 0));
+    const uint32_t pk = s.join_part_keys;
+    return s.wg_threads == 256 && s.wgs_per_cu >= 1 && s.wgs_per_cu <= 8 && s.join_wgs_per_cu >= 1 &&
+           s.join_wgs_per_cu <= 4 && s.item_rows >= 1024 &&
+           s.count_mode <= 2 && pk >= 128 && pk <= 65536 && (pk & (pk - 1)) == 0;
 }
 
-static BatchArgsHost make_args(gace_ctx* c, uint64_t force_cap) {
+static BatchArgsHost make_args(gace_ctx* c) {
     BatchArgsHost a;
     a.plan = c->d_plan;
     a.items = c->d_items;
@@ -76,21 +77,28 @@ static BatchArgsHost make_args(gace_ctx* c, uint64_t force_cap) {
     a.counts = c->d_counts;
     a.hist = c->d_hist;
     a.accs = c->d_accs;
-    a.sketch = c->d_sketch;
     a.arena_base = c->d_arena_base;
     a.arena = c->d_arena;
     a.count_mode = c->sched.count_mode;
-    a.cache_slots = c->sched.join_cache_slots;
-    a.force_cap = force_cap;
+    a.reserved = 0;
+    a.trace = c->d_trace;
     return a;
 }
 
-static uint32_t grid_of(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.wgs_per_cu; }
+static uint32_t scan_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.wgs_per_cu; }
+static uint32_t join_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.join_wgs_per_cu; }
 
-static gace_status launch_direct(gace_ctx* c, hipStream_t st, uint64_t force_cap) {
-    BatchArgsHost a = make_args(c, force_cap);
+// init kernel, then the scan kernel on st and the join kernel on the side
+// stream concurrently (they touch disjoint state), joined back into st
+static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side) {
+    BatchArgsHost a = make_args(c);
     HIP_TRY(gace_launch_init(c->d_plan, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st), "init kernel");
-    HIP_TRY(gace_launch_batch(&a, grid_of(c), st), "batch kernel");
+    HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
+    HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
+    HIP_TRY(gace_launch_join(&a, join_grid(c), side), "join kernel");
+    HIP_TRY(gace_launch_scan(&a, scan_grid(c), st), "scan kernel");
+    HIP_TRY(hipEventRecord(c->ev_join, side), "join event");
+    HIP_TRY(hipStreamWaitEvent(st, c->ev_join, 0), "join wait");
     return GACE_OK;
 }
 
@@ -105,7 +113,7 @@ static gace_status ensure_graph(gace_ctx* c) {
     if (c->graph_exec && std::memcmp(&c->graph_sched, &c->sched, sizeof(gace_schedule)) == 0) return GACE_OK;
     drop_graph(c);
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    gace_status st = launch_direct(c, c->cap_stream, 0);
+    gace_status st = launch_direct(c, c->cap_stream, c->cap_side);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (st != GACE_OK) {
@@ -120,7 +128,7 @@ static gace_status ensure_graph(gace_ctx* c) {
 }
 
 // upload a compiled batch, launch it and queue the result download on st
-gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool use_graph, uint64_t force_cap) {
+gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool use_graph) {
     const uint64_t plan_b = cb.plan.size(), items_b = cb.items.size() * sizeof(Item);
     const uint64_t accs_b = cb.jdesc.size() * sizeof(JoinAcc);
     auto too_big = [&](const char* what, uint64_t need, uint64_t cap) {
@@ -133,19 +141,20 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     if (cb.n_counts * 8ull > kCountsCap) return too_big("counts", cb.n_counts * 8ull, kCountsCap);
     if (cb.n_hist * 8ull > kHistCap) return too_big("sample histograms", cb.n_hist * 8ull, kHistCap);
     if (accs_b > kAccsCap) return too_big("join accumulators", accs_b, kAccsCap);
-    if (cb.sketch_bytes > kSketchCap) return too_big("join sketches", cb.sketch_bytes, kSketchCap);
+    if (cb.arena_static > c->arena_bytes) return too_big("join partition tables", cb.arena_static, c->arena_bytes);
 
     std::memcpy(c->h_stage, cb.plan.data(), plan_b);
+    ((PlanHdr*)c->h_stage)->trace = c->trace ? 1u : 0u;
     std::memcpy(c->h_stage + kPlanCap, cb.items.data(), items_b);
     HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, plan_b, hipMemcpyHostToDevice, st), "plan upload");
     if (items_b)
         HIP_TRY(hipMemcpyAsync(c->d_items, c->h_stage + kPlanCap, items_b, hipMemcpyHostToDevice, st), "item upload");
     HIP_TRY(hipEventRecord(c->ev0, st), "event");
-    if (use_graph && force_cap == 0) {
+    if (use_graph) {
         if (gace_status s = ensure_graph(c)) return s;
         HIP_TRY(hipGraphLaunch(c->graph_exec, st), "graph launch");
     } else {
-        if (gace_status s = launch_direct(c, st, force_cap)) return s;
+        if (gace_status s = launch_direct(c, st, c->side_stream)) return s;
     }
     HIP_TRY(hipEventRecord(c->ev1, st), "event");
     uint8_t* hc = c->h_result;
@@ -156,13 +165,18 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     if (cb.n_hist)
         HIP_TRY(hipMemcpyAsync(hh, c->d_hist, cb.n_hist * 8ull, hipMemcpyDeviceToHost, st), "hist download");
     if (accs_b) HIP_TRY(hipMemcpyAsync(ha, c->d_accs, accs_b, hipMemcpyDeviceToHost, st), "join download");
+    if (c->trace) {
+        c->last_trace.resize(cb.items.size());
+        if (!cb.items.empty())
+            HIP_TRY(hipMemcpyAsync(c->last_trace.data(), c->d_trace, cb.items.size() * sizeof(TraceRec),
+                                   hipMemcpyDeviceToHost, st), "trace download");
+    }
     HIP_TRY(hipEventRecord(c->ev_done, st), "event");
     return GACE_OK;
 }
 
 // after the batch's done event: write per-request outputs
-gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
-                            hipStream_t st, uint64_t force_cap) {
+gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_kernel_ms = ms;
     const uint8_t* hc = c->h_result;
@@ -191,29 +205,17 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
         rp += rows * so.n_preds;
         if (per_req) per_req[so.req] = GACE_OK;
     }
-    // copy join accumulators first: a rerun below reuses the result buffer
-    std::vector<JoinAcc> acc_copy(accs, accs + cb.jdesc.size());
     gace_status worst = GACE_OK;
     for (const JoinOut& jo : cb.joins) {
-        const JoinAcc& A = acc_copy[jo.join];
+        const JoinAcc& A = accs[jo.join];
         const gace_request& r = reqs[jo.req];
         gace_status s = GACE_OK;
-        c->learned_cap[join_identity(r)] = A.cap;
-        if (A.status == 1 && force_cap == 0) {
-            // the sketch-sized table filled up: rerun this join alone at the bound capacity
-            CompiledBatch one;
-            CompileOptions opt;
-            opt.item_rows = c->sched.item_rows;
-            compile_batch(&r, 1, opt, one);
-            gace_status ps = GACE_OK;
-            s = run_compiled(c, one, &r, &ps, st, false, one.jdesc[0].cap_max);
-            if (s == GACE_OK) s = ps;
-        } else if (A.status == 1) {
-            set_error("join hash table overflow at the bound capacity");
-            s = GACE_EDEVICE;
-        } else if (A.status == 2) {
-            set_error("workspace arena too small for the join hash tables of this batch");
+        if (A.status == 2) {
+            set_error("workspace arena too small for the partitioned join keys of this batch");
             s = GACE_ENOMEM;
+        } else if (A.status != 0) {
+            set_error("join aggregation could not split a partition further");
+            s = GACE_EDEVICE;
         } else {
             r.join->join_card = A.join;
             r.join->ndv_R = A.ndv[0];
@@ -231,24 +233,17 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
 }
 
 gace_status run_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
-                         hipStream_t st, bool use_graph, uint64_t force_cap) {
-    if (gace_status s = launch_compiled(c, cb, st, use_graph, force_cap)) return s;
+                         hipStream_t st, bool use_graph) {
+    if (gace_status s = launch_compiled(c, cb, st, use_graph)) return s;
     HIP_TRY(hipEventSynchronize(c->ev_done), "synchronize");
-    return finish_compiled(c, cb, reqs, per_req, st, force_cap);
-}
-
-std::string join_identity(const gace_request& r) {
-    std::ostringstream os;
-    os << (const void*)r.R.keys << ":" << r.R.n << ":" << r.R.table_id << ":" << r.R.spec.seed << ":"
-       << r.R.spec.rate << ":" << r.R.spec.block_rows << "|" << (const void*)r.S.keys << ":" << r.S.n << ":"
-       << r.S.table_id << ":" << r.S.spec.seed << ":" << r.S.spec.rate << ":" << r.S.spec.block_rows;
-    return os.str();
+    return finish_compiled(c, cb, reqs, per_req);
 }
 
 gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace_status* per_req, hipStream_t st,
                          bool use_graph) {
     CompileOptions opt;
     opt.item_rows = c->sched.item_rows;
+    opt.join_part_keys = c->sched.join_part_keys;
     CompiledBatch cb;
     compile_batch(reqs, n, opt, cb);
     gace_status first = GACE_OK;
@@ -262,7 +257,7 @@ gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace
     if (cb.sel.empty() && cb.joins.empty()) return first;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "set device");
-    gace_status s = run_compiled(c, cb, reqs, per_req, st, use_graph, 0);
+    gace_status s = run_compiled(c, cb, reqs, per_req, st, use_graph);
     if (first == GACE_OK) first = s;
     return first;
 }
@@ -336,21 +331,29 @@ gace_status gace_create(int hip_device, uint64_t workspace_bytes, gace_ctx** out
     c->d_counts = (unsigned long long*)p; p += kCountsCap;
     c->d_hist = (unsigned long long*)p; p += kHistCap;
     c->d_accs = (JoinAcc*)p; p += kAccsCap;
-    c->d_sketch = p; p += kSketchCap;
     c->d_head = (uint32_t*)p;
     c->d_arena = (Arena*)(p + 256);
     p += kMiscCap;
+    c->d_trace = (TraceRec*)p;
+    p += kTraceCap;
     c->d_arena_base = p;
     c->arena_bytes = workspace_bytes - kFixedBytes;
     if (hipHostMalloc((void**)&c->h_stage, kPlanCap + kItemsCap, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_result, kCountsCap + kHistCap + kAccsCap, hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap_side, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         gace_destroy(c);
         set_error("pinned staging / event / stream creation failed");
         return GACE_EDEVICE;
     }
+    int wall_khz = 0;
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && wall_khz > 0)
+        c->ticks_per_us = wall_khz / 1000.0;
     Arena ar;
     ar.used = 0;
     ar.size = c->arena_bytes;
@@ -371,6 +374,10 @@ gace_status gace_destroy(gace_ctx* c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev_done) (void)hipEventDestroy(c->ev_done);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+    if (c->cap_side) (void)hipStreamDestroy(c->cap_side);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_result) (void)hipHostFree(c->h_result);
@@ -450,6 +457,28 @@ gace_status gace_set_schedule(gace_ctx* ctx, const gace_schedule* s) {
     return GACE_OK;
 }
 
+gace_status gace_set_trace(gace_ctx* ctx, int enable) {
+    if (!ctx) {
+        set_error("NULL context");
+        return GACE_EINVAL;
+    }
+    ctx->trace = enable != 0;
+    return GACE_OK;
+}
+
+gace_status gace_get_trace(gace_ctx* ctx, gace_trace_rec* out, uint32_t cap, uint32_t* n, double* ticks_per_us) {
+    if (!ctx || (cap && !out)) {
+        set_error("NULL argument");
+        return GACE_EINVAL;
+    }
+    const uint32_t k = (uint32_t)std::min<size_t>(cap, ctx->last_trace.size());
+    static_assert(sizeof(gace_trace_rec) == sizeof(TraceRec), "trace record layout");
+    if (k) std::memcpy(out, ctx->last_trace.data(), k * sizeof(TraceRec));
+    if (n) *n = (uint32_t)ctx->last_trace.size();
+    if (ticks_per_us) *ticks_per_us = ctx->ticks_per_us;
+    return GACE_OK;
+}
+
 gace_status gace_last_batch_stats(gace_ctx* ctx, double* kernel_ms, uint64_t* alg_bytes, uint64_t* rows_preds) {
     if (!ctx) {
         set_error("NULL context");
@@ -466,7 +495,7 @@ static std::string sched_json(const gace_schedule& s) {
     std::ostringstream os;
     os << "{\"wg_threads\": " << s.wg_threads << ", \"wgs_per_cu\": " << s.wgs_per_cu
        << ", \"item_rows\": " << s.item_rows << ", \"count_mode\": " << s.count_mode
-       << ", \"join_cache_slots\": " << s.join_cache_slots << "}";
+       << ", \"join_part_keys\": " << s.join_part_keys << ", \"join_wgs_per_cu\": " << s.join_wgs_per_cu << "}";
     return os.str();
 }
 
@@ -495,7 +524,8 @@ static void load_cache(gace_ctx* c, const char* path, const std::string& prefix)
         parse_u32(line, "wgs_per_cu", s.wgs_per_cu);
         parse_u32(line, "item_rows", s.item_rows);
         parse_u32(line, "count_mode", s.count_mode);
-        parse_u32(line, "join_cache_slots", s.join_cache_slots);
+        parse_u32(line, "join_part_keys", s.join_part_keys);
+        parse_u32(line, "join_wgs_per_cu", s.join_wgs_per_cu);
         if (valid_schedule(s)) c->tuned[key.substr(prefix.size())] = s;
     }
 }
@@ -554,7 +584,8 @@ gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, c
     const uint32_t wgs[] = {1, 2, 3, 4};
     const uint32_t rows[] = {16384, 32768, 65536, 131072, 262144};
     const uint32_t modes[] = {0, 1, 2};
-    const uint32_t caches[] = {0, 1024, 2048};
+    const uint32_t parts[] = {512, 1024, 2048};
+    const uint32_t jwgs[] = {2, 3, 4};
     for (int pass = 0; pass < 2; ++pass) {
         for (uint32_t v : wgs) {
             gace_schedule s = best; s.wgs_per_cu = v; double ms;
@@ -568,8 +599,12 @@ gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, c
             gace_schedule s = best; s.count_mode = v; double ms;
             if (time_it(s, ms) == GACE_OK && ms < best_ms) { best = s; best_ms = ms; }
         }
-        for (uint32_t v : caches) {
-            gace_schedule s = best; s.join_cache_slots = v; double ms;
+        for (uint32_t v : parts) {
+            gace_schedule s = best; s.join_part_keys = v; double ms;
+            if (time_it(s, ms) == GACE_OK && ms < best_ms) { best = s; best_ms = ms; }
+        }
+        for (uint32_t v : jwgs) {
+            gace_schedule s = best; s.join_wgs_per_cu = v; double ms;
             if (time_it(s, ms) == GACE_OK && ms < best_ms) { best = s; best_ms = ms; }
         }
     }

@@ -19,11 +19,13 @@ constexpr uint64_t kItemsCap = 8ull << 20;
 constexpr uint64_t kCountsCap = 8ull << 20;
 constexpr uint64_t kHistCap = 4ull << 20;
 constexpr uint64_t kAccsCap = 1ull << 20;
-constexpr uint64_t kSketchCap = 64ull << 20;
 constexpr uint64_t kMiscCap = 4096;
-constexpr uint64_t kFixedBytes = kPlanCap + kItemsCap + kCountsCap + kHistCap + kAccsCap + kSketchCap + kMiscCap;
+constexpr uint64_t kTraceCap = (kItemsCap / sizeof(Item)) * sizeof(TraceRec);
+constexpr uint64_t kFixedBytes = kPlanCap + kItemsCap + kCountsCap + kHistCap + kAccsCap + kMiscCap + kTraceCap;
 
 }  // namespace gace
+
+using gace::TraceRec;
 
 struct gace_ctx {
     int device = 0;
@@ -36,26 +38,29 @@ struct gace_ctx {
     unsigned long long* d_counts = nullptr;
     unsigned long long* d_hist = nullptr;
     gace::JoinAcc* d_accs = nullptr;
-    uint8_t* d_sketch = nullptr;
     uint32_t* d_head = nullptr;
+    TraceRec* d_trace = nullptr;
     gace::Arena* d_arena = nullptr;
     uint8_t* d_arena_base = nullptr;
     uint64_t arena_bytes = 0;
     // pinned host staging
     uint8_t* h_stage = nullptr;     // plan + items upload
     uint8_t* h_result = nullptr;    // counts + hist + accs download
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr, ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t side_stream = nullptr;   // join kernel runs here, concurrently with the scan kernel
     gace_schedule sched{};
     // graph of (init kernel, batch kernel) for the current schedule
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     gace_schedule graph_sched{};
-    hipStream_t cap_stream = nullptr;
+    hipStream_t cap_stream = nullptr, cap_side = nullptr;
     // stats of the last batch
     double last_kernel_ms = 0.0;
     uint64_t last_alg_bytes = 0, last_rows_preds = 0;
     std::map<std::string, gace_schedule> tuned;   // shape bucket -> schedule
-    std::map<std::string, uint64_t> learned_cap;  // join identity -> table slots chosen last time
+    bool trace = false;                           // record per-item device timestamps
+    std::vector<TraceRec> last_trace;
+    double ticks_per_us = 0.0;
 };
 
 namespace gace {
@@ -66,12 +71,10 @@ gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace
                          bool use_graph);
 
 std::string shape_bucket(const gace_request* reqs, uint32_t n);
-std::string join_identity(const gace_request& r);
 
-gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool use_graph, uint64_t force_cap);
-gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
-                            hipStream_t st, uint64_t force_cap);
+gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool use_graph);
+gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req);
 gace_status run_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
-                         hipStream_t st, bool use_graph, uint64_t force_cap);
+                         hipStream_t st, bool use_graph);
 
 }  // namespace gace

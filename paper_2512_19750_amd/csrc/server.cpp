@@ -47,7 +47,10 @@ struct TicketState {
     gace_status st = GACE_OK;
 };
 
-uint64_t slots_for_join(const gace_request& r) {
+// device bytes a join needs: its partitioned key buffer (8 bytes per sampled
+// key, bounded by the expected kept blocks plus 12 standard deviations) and
+// its per-item partition tables
+uint64_t join_bytes(const gace_request& r) {
     uint64_t U = 0;
     const gace_keys* s[2] = {&r.R, &r.S};
     for (int i = 0; i < 2; ++i) {
@@ -59,9 +62,7 @@ uint64_t slots_for_join(const gace_request& r) {
         uint64_t k = kept >= (double)nb ? nb : (uint64_t)kept;
         U += std::min<uint64_t>(s[i]->n, k * B);
     }
-    uint64_t cap = 2048;
-    while (cap < 2 * U) cap <<= 1;
-    return cap;
+    return 8 * U + (U / 2048) * 4 * 8192 / 64 + (1ull << 20);
 }
 
 }  // namespace
@@ -74,7 +75,6 @@ struct gace_server {
     std::condition_variable cv_work, cv_done;
     std::deque<std::unique_ptr<OwnedRequest>> queue;
     std::unordered_map<uint64_t, TicketState> tickets;
-    std::unordered_map<std::string, uint64_t> learned;   // join identity -> table slots
     uint64_t next_ticket = 1;
     uint64_t slot_budget = 0;
     bool stop = false;
@@ -93,7 +93,7 @@ bool gace_server::try_complete(ServeSlot& s, std::unique_lock<std::mutex>& lk) {
     lk.unlock();
     gace_status bst = GACE_OK;
     if (q == hipSuccess) {
-        bst = gace::finish_compiled(s.ctx, s.cb, s.arr.data(), s.per.data(), s.stream, 0);
+        bst = gace::finish_compiled(s.ctx, s.cb, s.arr.data(), s.per.data());
         (void)bst;
     } else {
         for (auto& p : s.per) p = GACE_EDEVICE;
@@ -101,10 +101,6 @@ bool gace_server::try_complete(ServeSlot& s, std::unique_lock<std::mutex>& lk) {
     lk.lock();
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         OwnedRequest& o = *s.reqs[i];
-        if (o.r.kind == GACE_REQ_JOIN && s.per[i] == GACE_OK) {
-            auto it = s.ctx->learned_cap.find(gace::join_identity(s.arr[i]));
-            if (it != s.ctx->learned_cap.end()) learned[gace::join_identity(s.arr[i])] = it->second;
-        }
         TicketState& t = tickets[o.ticket];
         t.done = true;
         t.st = s.per[i];
@@ -144,8 +140,9 @@ bool gace_server::try_launch(ServeSlot& s, std::unique_lock<std::mutex>& lk) {
     lk.unlock();
     gace::CompileOptions opt;
     opt.item_rows = s.ctx->sched.item_rows;
+    opt.join_part_keys = s.ctx->sched.join_part_keys;
     gace::compile_batch(s.arr.data(), (uint32_t)s.arr.size(), opt, s.cb);
-    gace_status st = gace::launch_compiled(s.ctx, s.cb, s.stream, true, 0);
+    gace_status st = gace::launch_compiled(s.ctx, s.cb, s.stream, true);
     lk.lock();
     if (st != GACE_OK) {
         for (auto& o : s.reqs) {
@@ -251,9 +248,7 @@ gace_status gace_server_submit(gace_server* srv, const gace_request* req, uint64
     }
     std::lock_guard<std::mutex> g(srv->mu);
     if (req->kind == GACE_REQ_JOIN) {
-        auto it = srv->learned.find(gace::join_identity(*req));
-        const uint64_t slots = it != srv->learned.end() ? it->second : slots_for_join(*req);
-        o->ws_est = slots * sizeof(gace::Slot);
+        o->ws_est = join_bytes(*req);
         if (o->ws_est > srv->slot_budget) {
             srv->stats.rejected += 1;
             set_error("request needs " + std::to_string(o->ws_est) + " workspace bytes; a slot has " +

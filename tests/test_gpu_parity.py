@@ -196,7 +196,7 @@ def test_join_small_vs_oracle(g, ctx, torch_dev, case):
     assert got == want
 
 
-@pytest.mark.parametrize("cache", [0, 1024])
+@pytest.mark.parametrize("cache", [256, 4096])
 def test_join_cache_settings_agree(g, torch_dev, cache):
     import torch
     w = datagen.config3(rate=1.0, n_r=2_000_000, n_s=500_000, domain=100_000)
@@ -205,7 +205,7 @@ def test_join_cache_settings_agree(g, torch_dev, cache):
     ks = datagen.device_column(jr.s.cols[0], jr.s.n_rows, torch_dev)
     c = g.gace_create(0, 2 << 30)
     try:
-        g.gace_set_schedule(c, join_cache_slots=cache)
+        g.gace_set_schedule(c, join_part_keys=cache)
         got = _join(g, c, kr, ks, jr.r.table_id, jr.s.table_id, jr.spec_r.seed, jr.spec_s.seed, 1.0, 1.0)
     finally:
         g.gace_destroy(c)
@@ -301,7 +301,7 @@ def test_batch_repeatable_and_schedules_agree(g, torch_dev):
     try:
         results = []
         for sched in [dict(), dict(wgs_per_cu=1, item_rows=16384), dict(wgs_per_cu=3, count_mode=1, item_rows=262144),
-                      dict(count_mode=2, join_cache_slots=0)]:
+                      dict(count_mode=2, join_part_keys=512)]:
             if sched:
                 g.gace_set_schedule(c, **sched)
             for rep in range(2):

@@ -1,0 +1,137 @@
+"""Serving path on the GPU: requests submitted from several threads while other
+batches run are admitted, batched and completed; every result equals the
+request's plain-path result and the oracle's (alone == in the mix)."""
+import threading
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2512_19750_amd as g
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    w = datagen.config4(scale=0.003, n_sel=80, n_join=10, seed_offset=11)
+    tabs, keys = datagen.materialise(w, dev)
+    return g, w, tabs, keys
+
+
+def _req(g, w, tabs, keys, kind, i):
+    if kind == "sel":
+        r = w.sel[i]
+        t = w.tables[r.table]
+        return g.SelRequest(g.Table(tabs[r.table], t.table_id), r.preds, r.spec.seed, r.spec.rate, r.spec.block_rows)
+    j = w.joins[i]
+    kr, ks = keys[i]
+    return g.JoinRequest(g.Keys(kr, j.r.table_id, j.spec_r.seed, j.spec_r.rate, j.spec_r.block_rows),
+                         g.Keys(ks, j.s.table_id, j.spec_s.seed, j.spec_s.rate, j.spec_s.block_rows))
+
+
+def _res(g, q):
+    if isinstance(q, g.JoinRequest):
+        return q.result()
+    c, n, b = q.result()
+    return (c.tolist(), n, b)
+
+
+def test_served_results_equal_alone_and_oracle(env):
+    g, w, tabs, keys = env
+    order = list(w.order)
+    # results alone (plain path)
+    ctx = g.gace_create(0, 2 << 30)
+    alone = {}
+    try:
+        for kind, i in order:
+            q = _req(g, w, tabs, keys, kind, i)
+            if kind == "sel":
+                c, n, b = g.gace_probe_selectivity(ctx, q.table, q.preds, q.seed, q.rate, q.block_rows)
+                alone[(kind, i)] = (c.tolist(), n, b)
+            else:
+                alone[(kind, i)] = g.gace_join_freq(ctx, q.R, q.S)
+    finally:
+        g.gace_destroy(ctx)
+    # served: 4 submitting threads, small batches so several batches overlap
+    srv = g.gace_server_create(0, max_inflight=3, max_batch=16, queue_capacity=1024, workspace_bytes=6 << 30)
+    served = {}
+    errors = []
+    try:
+        def worker(part):
+            try:
+                mine = []
+                for kind, i in part:
+                    q = _req(g, w, tabs, keys, kind, i)
+                    mine.append(((kind, i), q, g.gace_server_submit(srv, q)))
+                for key, q, t in mine:
+                    st = g.gace_server_wait(srv, t, 60_000_000_000)
+                    served[key] = (st, _res(g, q))
+            except Exception as e:  # surfaced below
+                errors.append(e)
+        threads = [threading.Thread(target=worker, args=(order[k::4],)) for k in range(4)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        stats = g.gace_server_stats_get(srv)
+    finally:
+        g.gace_server_destroy(srv)
+    assert not errors, errors
+    assert stats["completed"] == len(order) and stats["batches"] >= 2
+    for key in alone:
+        st, res = served[key]
+        assert st == 0, key
+        assert res == alone[key], key
+    # and against the oracle for a sample of requests
+    for kind, i in order[:: max(1, len(order) // 12)]:
+        if kind == "sel":
+            c, n, b = oracle.sel_request(w, i)
+            assert alone[(kind, i)] == (c.tolist(), n, b)
+        else:
+            assert alone[(kind, i)] == oracle.join_request(w, i)
+
+
+def test_server_rejects_invalid_and_oversized(env):
+    g, w, tabs, keys = env
+    srv = g.gace_server_create(0, max_inflight=1, max_batch=8, queue_capacity=8, workspace_bytes=512 << 20)
+    try:
+        import torch
+        bad = g.SelRequest(g.Table(tabs[0], 100), [[(7, g.EQ, (1,))]])
+        with pytest.raises(g.GaceError) as e:
+            g.gace_server_submit(srv, bad)
+        assert e.value.status == g.GACE_EINVAL
+        big = torch.zeros(200_000_000, dtype=torch.int64, device="cuda")
+        huge = g.JoinRequest(g.Keys(big, 1), g.Keys(big, 2))
+        with pytest.raises(g.GaceError) as e:
+            g.gace_server_submit(srv, huge)
+        assert e.value.status == g.GACE_ENOMEM
+        ok = _req(g, w, tabs, keys, "sel", 0)
+        t = g.gace_server_submit(srv, ok)
+        assert g.gace_server_wait(srv, t, 60_000_000_000) == 0
+        st = g.gace_server_stats_get(srv)
+        assert st["rejected"] == 2 and st["completed"] == 1
+        del big
+    finally:
+        g.gace_server_destroy(srv)
+
+
+def test_tracing_records_every_item(env):
+    g, w, tabs, keys = env
+    ctx = g.gace_create(0, 2 << 30)
+    try:
+        reqs = [_req(g, w, tabs, keys, k, i) for k, i in w.order[:40]]
+        g.gace_set_trace(ctx, True)
+        g.gace_batch_run(ctx, reqs)
+        tr, tpu = g.gace_get_trace(ctx)
+        assert len(tr) > 0 and tpu > 0
+        assert np.all(tr["t_end"] >= tr["t_ready"]) and np.all(tr["t_ready"] >= tr["t_begin"])
+        assert set(np.unique(tr["kind"]).tolist()) <= {1, 2, 3, 4, 5, 6}
+        assert np.all(tr["xcc"] < 16)
+    finally:
+        g.gace_destroy(ctx)
