@@ -27,21 +27,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2512_19750_amd", "csrc", "kernels.hip")
-COUNTERS = os.path.join(ROOT, "profiles", "gace_batch_kernel_c4_counters.md")
+CSRC = os.path.join(ROOT, "paper_2512_19750_amd", "csrc")
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("kernels.hip", "plan.h", "compile.cpp")]
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources that decide what the kernels read and write."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def stored_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
-    if not os.path.exists(COUNTERS):
+def counters_path(kernel: str) -> str:
+    return os.path.join(ROOT, "profiles", "%s_c4_counters.md" % kernel)
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    path = counters_path(kernel)
+    if not os.path.exists(path):
         return None
-    txt = open(COUNTERS).read()
+    txt = open(path).read()
     h = None
     t = None
     for line in txt.splitlines():
@@ -114,6 +123,186 @@ def cpu_baseline(w, budget_rows_preds: float, nthreads: int):
                        % (len(picked), len(w.sel), rows_done, rp_done))
 
 
+# ---------------------------------------------------------------- serving
+def _pct(xs, q):
+    if not xs:
+        return None
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, max(0, int(math.ceil(q * len(xs))) - 1))]
+
+
+def serve_point(g, pool_arr, expect, kinds, qps, cfg, seed, duration_s=10.0, max_req=20000, warm_s=1.0,
+                ring=8192):
+    """Open-loop Poisson arrivals at `qps` for duration_s (or max_req
+    requests), each request drawn uniformly from the pool.  Latency = the
+    server's completion time - the scheduled arrival time; arrivals in the
+    first warm_s seconds are not counted.  Every served result is compared
+    with the pool entry's plain-path result."""
+    import ctypes
+    import queue as _q
+    import threading
+
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    n = int(min(max_req, qps * duration_s))
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, n))
+    picks = rng.integers(0, len(kinds), n)
+    ring_arr = (g.gace_request * ring)()
+    counts = np.zeros((ring, 32), dtype=np.uint64)
+    infos = (g.gace_probe_info * ring)()
+    jres = (g.gace_join_result * ring)()
+    cptr = [counts[i].ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) for i in range(ring)]
+    iptr = [ctypes.pointer(infos[i]) for i in range(ring)]
+    jptr = [ctypes.pointer(jres[i]) for i in range(ring)]
+    srv = g.gace_server_create(0, **cfg)
+    work = _q.Queue()
+    lat, bad, done_t, seen = [], [0], [], [0]
+
+    def waiter():
+        while True:
+            item = work.get()
+            if item is None:
+                return
+            i, slot, t, sched = item
+            if t is None:          # rejected with EBUSY: nothing to read
+                seen[0] = i + 1
+                continue
+            st, _, t_done = g.gace_server_wait_times(srv, t, -1)
+            p = int(picks[i])
+            if kinds[p] == "join":
+                o = jres[slot]
+                got = (int(o.join_card), int(o.ndv_R), int(o.ndv_S), int(o.n_R), int(o.n_S))
+            else:
+                k = len(expect[p][0])
+                got = (tuple(int(x) for x in counts[slot][:k]), int(infos[slot].sampled_rows),
+                       int(infos[slot].kept_blocks))
+            if st != 0 or got != expect[p]:
+                bad[0] += 1
+            if arrivals[i] >= warm_s:
+                lat.append((t_done - sched) / 1e6)
+                done_t.append(t_done)
+            seen[0] = i + 1
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    busy = 0
+    t0 = time.monotonic_ns() + 20_000_000
+    try:
+        for i in range(n):
+            sched = t0 + int(arrivals[i] * 1e9)
+            while True:
+                now = time.monotonic_ns()
+                if now >= sched:
+                    break
+                if sched - now > 300_000:
+                    time.sleep((sched - now - 200_000) / 1e9)
+            slot = i % ring
+            while seen[0] + ring <= i and th.is_alive():   # slot's previous result not read yet
+                time.sleep(1e-4)
+            p = int(picks[i])
+            r = ring_arr[slot]
+            ctypes.memmove(ctypes.byref(r), ctypes.byref(pool_arr[p]), ctypes.sizeof(g.gace_request))
+            if kinds[p] == "join":
+                r.join = jptr[slot]
+            else:
+                r.counts = cptr[slot]
+                r.info = iptr[slot]
+            try:
+                t = g.gace_server_submit_raw(srv, ctypes.byref(r))
+            except g.GaceError as e:
+                if e.status != g.GACE_EBUSY:
+                    raise
+                busy += 1
+                t = None
+            work.put((i, slot, t, sched))
+    finally:
+        work.put(None)
+        th.join()
+        stats = g.gace_server_stats_get(srv)
+        g.gace_server_destroy(srv)
+    t_first = t0 + int(warm_s * 1e9)
+    span = (max(done_t) - t_first) / 1e9 if done_t else 0.0
+    return dict(qps=qps, offered=n, counted=len(lat), rejected_busy=busy, mismatches=bad[0],
+                p50_ms=round(_pct(lat, 0.50), 3) if lat else None, p99_ms=round(_pct(lat, 0.99), 3) if lat else None,
+                throughput_rps=round(len(lat) / span, 1) if span > 0 else None, batches=stats["batches"],
+                workspace_peak=stats["workspace_peak"])
+
+
+def serve_main(args):
+    import torch
+
+    import datagen
+    import paper_2512_19750_amd as g
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_setup = time.time()
+    w = datagen.config5(scale=args.scale)
+    tabs, keys = datagen.materialise(w, dev)
+    torch.cuda.synchronize()
+    resident = sum(c.numel() * c.element_size() for t in tabs for c in t) + \
+        sum(k.numel() * 8 for pair in keys for k in pair)
+    print("[serve] %d tables + %d join pairs, %.1f GB resident, %.1fs" % (len(tabs), len(keys), resident / 1e9,
+                                                                       time.time() - t_setup),
+          file=sys.stderr, flush=True)
+    pool = build_requests(g, w, tabs, keys)
+    kinds = [k for k, _ in w.order]
+    pool_arr, keep = g.make_requests(pool)
+    # plain-path results of every pool entry (each served result must equal them)
+    free_b, _ = torch.cuda.mem_get_info()
+    ctx = g.gace_create(0, int(min(24 << 30, free_b * 0.8)))
+    t0 = time.time()
+    expect, plain_lat = [], []
+    for q in pool:
+        s0 = time.perf_counter()
+        if isinstance(q, g.JoinRequest):
+            r = g.gace_join_freq(ctx, q.R, q.S)
+            expect.append((r["join_card"], r["ndv_R"], r["ndv_S"], r["n_R"], r["n_S"]))
+        else:
+            c, nrow, nblk = g.gace_probe_selectivity(ctx, q.table, q.preds, q.seed, q.rate, q.block_rows)
+            expect.append((tuple(int(x) for x in c), nrow, nblk))
+        plain_lat.append((time.perf_counter() - s0) * 1e3)
+    g.gace_destroy(ctx)
+    plain_s = time.time() - t0
+    print("[serve] plain path over the pool: %.1fs (%.1f req/s)" % (plain_s, len(pool) / plain_s), file=sys.stderr,
+          flush=True)
+    free_b, _ = torch.cuda.mem_get_info()
+    ws = int(min(args.serve_workspace_gb * (1 << 30), free_b * 0.8))
+    modes = {
+        "batched": dict(max_inflight=3, max_batch=64, queue_capacity=4096, workspace_bytes=ws),
+        "fifo_one_launch_per_request": dict(max_inflight=1, max_batch=1, queue_capacity=4096,
+                                            workspace_bytes=ws // 3),
+    }
+    points = []
+    for qps in [int(x) for x in args.serve_qps.split(",")]:
+        for name, cfg in modes.items():
+            r = serve_point(g, pool_arr, expect, kinds, qps, cfg, seed=S_SERVE + qps,
+                            duration_s=args.serve_seconds)
+            r["mode"] = name
+            points.append(r)
+            print("[serve] %s" % json.dumps(r), file=sys.stderr, flush=True)
+    out = {
+        "metric": "served probe latency (completion - scheduled Poisson arrival) and throughput",
+        "unit": "ms",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "data": "synthetic (seeded counter-based generator, generated in HBM)",
+        "config": {"workload": "C5 served probe stream: %d tables of config 4's size law + 64 join pairs, "
+                               "%.1f GB resident, pool of %d requests from config 4's mix (%d joins)%s"
+                               % (len(tabs), resident / 1e9, len(pool), kinds.count("join"),
+                                  "" if args.scale == 1.0 else " (scale %g)" % args.scale),
+                   "arrivals": "open-loop Poisson, %gs or 20000 requests per point, first 1s not counted"
+                               % args.serve_seconds},
+        "plain_path_pool": {"seconds": round(plain_s, 3),
+                            "latency_ms_p50": round(_pct(plain_lat, 0.5), 4),
+                            "latency_ms_p99": round(_pct(plain_lat, 0.99), 4)},
+        "points": points,
+    }
+    print(json.dumps(out))
+
+
+S_SERVE = 0x2512197500 + 40
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,11 +316,23 @@ def main():
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2512_19750_amd", "tuned_schedules.jsonl"))
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only copy this many bytes device-to-device 3 times (counter calibration) and exit")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the served probe stream (config 5) instead of the batch benchmark")
+    ap.add_argument("--serve-qps", default="100,200,500,1000,2000,5000")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-workspace-gb", type=float, default=60.0)
+    ap.add_argument("--serve-point-qps", type=float, default=1000.0,
+                    help="batch benchmark: also serve its requests at this Poisson rate (0: skip)")
+    ap.add_argument("--serve-point-seconds", type=float, default=5.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the probe on a single MI355X "
               "(multi-GPU sharding is a design note, not a code path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        serve_main(args)
+        return
 
     import torch
 
@@ -167,14 +368,21 @@ def main():
         g.gace_autotune(ctx, reqs, args.tune_cache)
         print("[bench] schedule %s (%.1fs)" % (g.gace_get_schedule(ctx), time.time() - t0), file=sys.stderr,
               flush=True)
+    # timed region: direct launches, so that HIP events bracket each kernel on
+    # its own stream (scan kernel on the call's stream, join kernel on the side
+    # stream); results are identical to graph replay, which is timed after
+    g.gace_set_graph(ctx, False)
     for _ in range(args.warmup):
         g.gace_batch_run(ctx, reqs, prepared=prepared)
     torch.cuda.synchronize()
-    kms = []
+    kms, sms, jms = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g.gace_batch_run(ctx, reqs, prepared=prepared)
         kms.append(g.gace_last_batch_stats(ctx)["kernel_ms"])
+        ks = g.gace_last_kernel_stats(ctx)
+        sms.append(ks["scan_ms"])
+        jms.append(ks["join_ms"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = g.gace_last_batch_stats(ctx)
@@ -182,7 +390,25 @@ def main():
     rows_preds = st["rows_preds"]
     value = rows_preds / (wall / args.steps)
     kernel_ms = sum(kms) / len(kms)
-    achieved = st["alg_bytes"] / (kernel_ms * 1e-3) / 1e9
+    per_kernel = {
+        "gace_scan_kernel": dict(ms=sum(sms) / len(sms), alg_bytes=ks["scan_alg_bytes"]),
+        "gace_join_kernel": dict(ms=sum(jms) / len(jms), alg_bytes=ks["join_alg_bytes"]),
+    }
+    for k in per_kernel.values():
+        k["achieved_gbps"] = k["alg_bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
+    dominant = max(per_kernel, key=lambda k: per_kernel[k]["ms"])
+    dk = per_kernel[dominant]
+    achieved = dk["achieved_gbps"]
+    traffic = stored_traffic(dominant)
+    # graph replay of the same batch (the batched path's default)
+    g.gace_set_graph(ctx, True)
+    g.gace_batch_run(ctx, reqs, prepared=prepared)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.gace_batch_run(ctx, reqs, prepared=prepared)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) / args.steps * 1e3
     sel_rows = 0
     join_keys = 0
     for q in reqs:
@@ -191,19 +417,23 @@ def main():
             join_keys += r["n_R"] + r["n_S"]
         else:
             sel_rows += q.result()[1]
-    print("[bench] batch %.2f ms/step (kernel %.2f ms), %.3g rows*preds/s" % (ms_step, kernel_ms, value),
-          file=sys.stderr, flush=True)
+    print("[bench] batch %.2f ms/step (kernels %.2f ms: scan %.2f, join %.2f; graph replay %.2f ms/step), "
+          "%.3g rows*preds/s" % (ms_step, kernel_ms, per_kernel["gace_scan_kernel"]["ms"],
+                                 per_kernel["gace_join_kernel"]["ms"], graph_ms, value), file=sys.stderr, flush=True)
 
     plain = None
+    expect = []
     if args.plain:
         lat = []
         t0 = time.perf_counter()
         for q in reqs:
             s = time.perf_counter()
             if isinstance(q, g.JoinRequest):
-                g.gace_join_freq(ctx, q.R, q.S)
+                r = g.gace_join_freq(ctx, q.R, q.S)
+                expect.append((r["join_card"], r["ndv_R"], r["ndv_S"], r["n_R"], r["n_S"]))
             else:
-                g.gace_probe_selectivity(ctx, q.table, q.preds, q.seed, q.rate, q.block_rows)
+                c, nrow, nblk = g.gace_probe_selectivity(ctx, q.table, q.preds, q.seed, q.rate, q.block_rows)
+                expect.append((tuple(int(x) for x in c), nrow, nblk))
             lat.append((time.perf_counter() - s) * 1e3)
         plain_s = time.perf_counter() - t0
         lat.sort()
@@ -214,6 +444,14 @@ def main():
               flush=True)
     sched = g.gace_get_schedule(ctx)
     g.gace_destroy(ctx)
+    # served: the same requests arriving as an open-loop Poisson stream
+    served = None
+    if args.plain and args.serve_point_qps > 0:
+        kinds = ["join" if isinstance(q, g.JoinRequest) else "sel" for q in reqs]
+        served = serve_point(g, prepared[0], expect, kinds, args.serve_point_qps,
+                             dict(max_inflight=3, max_batch=64, queue_capacity=4096, workspace_bytes=ws),
+                             seed=S_SERVE, duration_s=args.serve_point_seconds)
+        print("[bench] served %s" % json.dumps(served), file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:
@@ -240,7 +478,8 @@ def main():
             "workload": "C4 batched uneven probes: 448 selectivity requests (1-32 conjunctive predicates, "
                         "rate log-uniform 0.1-100%%, 4096-row blocks) over 16 tables of log-uniform 1e6-5e8 rows "
                         "x 4 int32 columns + 64 join-key frequency probes (Zipf 1.0 R / uniform S, 0.01-1 x "
-                        "(200M + 50M) keys, rate 1 or 0.05), one persistent graph-replayed launch%s"
+                        "(200M + 50M) keys, rate 1 or 0.05), one batched launch of the persistent scan and join "
+                        "kernels running concurrently%s"
                         % ("" if args.scale == 1.0 else " (scale %g)" % args.scale),
             "requests": len(reqs),
             "resident_bytes": resident,
@@ -255,12 +494,18 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": stored_traffic(),
-            "kernel": "gace_batch_kernel",
-            "alg_bytes_per_launch": st["alg_bytes"],
-            "kernel_ms": round(kernel_ms, 4),
+            "traffic": traffic,
+            "kernel": dominant,
+            "alg_bytes_per_launch": dk["alg_bytes"],
+            "kernel_ms": round(dk["ms"], 4),
         },
+        "kernels": {k: {"ms": round(v["ms"], 4), "alg_bytes": v["alg_bytes"],
+                        "achieved_gbps": round(v["achieved_gbps"], 1),
+                        "traffic": stored_traffic(k)} for k, v in per_kernel.items()},
+        "batch_kernel_span_ms": round(kernel_ms, 4),
+        "graph_replay_ms_per_step": round(graph_ms, 4),
         "join_keys_per_s": join_keys / (wall / args.steps),
+        "served": served,
         "plain_path": plain,
         "cpu_baseline": cpu,
     }

@@ -411,6 +411,38 @@ def config4(scale: float = 1.0, n_tables: int = 16, n_sel: int = 448, n_join: in
     return w
 
 
+def config5(scale: float = 1.0, target_bytes: float = 170e9, n_pool: int = 2048,
+            seed_offset: int = 0) -> Workload:
+    """Served probe stream: tables drawn from config 4's size law (log-uniform
+    1e6..5e8 rows x 4 i32 U[0,1000)) until they hold target_bytes (x scale),
+    config 4's 64 join-key pairs, and a pool of n_pool requests drawn from
+    config 4's mix (448 selectivity : 64 join) over them.  `order` is the pool;
+    a join pair may appear in it several times."""
+    rng = np.random.default_rng(S0 + 25 + seed_offset)
+    w4 = config4(scale=scale, seed_offset=seed_offset)
+    w = Workload("served probe stream: tables of config 4's size law up to %.3g bytes + 64 join pairs, "
+                 "pool of %d requests (scale %g)" % (target_bytes * scale, n_pool, scale))
+    lo, hi = math.log(1_000_000), math.log(500_000_000)
+    total = 0
+    while total < target_bytes * scale:
+        n = max(1, int(round(math.exp(rng.uniform(lo, hi)) * scale)))
+        w.tables.append(uniform_i32_table(n, 4, S0 + 5 + seed_offset, table_id=2000 + len(w.tables)))
+        total += n * 16
+    w.joins = w4.joins
+    table_seeds = [S0 + 3000 + 7 * t + seed_offset for t in range(len(w.tables))]
+    for _ in range(n_pool):
+        if rng.random() < 64.0 / 512.0:
+            w.order.append(("join", int(rng.integers(0, len(w.joins)))))
+            continue
+        ti = int(rng.integers(0, len(w.tables)))
+        p = int(rng.integers(1, 33))
+        preds = random_predicates(rng, w.tables[ti], p)
+        rate = float(math.exp(rng.uniform(math.log(0.001), 0.0)))
+        w.sel.append(SelRequest(ti, preds, SampleSpec(table_seeds[ti], rate, 4096)))
+        w.order.append(("sel", len(w.sel) - 1))
+    return w
+
+
 def workload_bytes(w: Workload) -> int:
     tb = sum(t.n_rows * t.row_bytes for t in w.tables)
     jb = sum((j.r.n_rows + j.s.n_rows) * 8 for j in w.joins)

@@ -225,13 +225,36 @@ gace_status gace_set_schedule(gace_ctx* ctx, const gace_schedule* s);
 /* Timing of the last gace_batch_run: device time of the persistent kernel
    in milliseconds, measured with HIP events on the call's stream, and the
    algorithmic HBM bytes it moved (kept rows x referenced column widths of
-   each shared scan + 8 bytes per sampled join key). */
+   each shared scan + 8 bytes per sampled join key + 16 bytes per distinct
+   key and side). */
 gace_status gace_last_batch_stats(gace_ctx* ctx, double* kernel_ms, uint64_t* alg_bytes,
                                   uint64_t* rows_preds);
 
+/* Per-kernel timing of the last gace_batch_run that ran by direct launch
+   (gace_set_graph(ctx, 0)): device time of the scan kernel, measured with HIP
+   events on the call's stream, and of the join kernel, measured on the
+   context's side stream where it runs concurrently; with the algorithmic HBM
+   bytes of each (scan: kept rows x referenced column widths per shared scan;
+   join: 8 bytes per sampled key + 16 bytes per distinct key and side).
+   timed = 0 and both times 0 after a graph-replayed batch. */
+typedef struct {
+    double scan_ms, join_ms;
+    uint64_t scan_alg_bytes, join_alg_bytes;
+    uint32_t timed;
+    uint32_t reserved;
+} gace_kernel_stats;
+
+gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out);
+
+/* Select how gace_batch_run launches: graph replay (enable != 0, the
+   default) or direct launches with per-kernel timing events.  Results are
+   identical. */
+gace_status gace_set_graph(gace_ctx* ctx, int enable);
+
 /* Per-item device trace of the last batch (for profiling the batched path).
    Item kinds: 1 scan, 2 join histogram, 3 join offsets, 4 join partition
-   starts, 5 join scatter, 6 join aggregation.  Timestamps are ticks of the
+   starts, 5 join scatter (first pass), 6 join aggregation, 7 join scatter
+   (second pass).  Timestamps are ticks of the
    device's constant-rate counter (ticks_per_us of them per microsecond):
    t_begin when a workgroup took the item, t_ready when its dependencies were
    met, t_end when it finished.  Tracing costs one store per item. */
@@ -276,6 +299,11 @@ gace_status gace_server_submit(gace_server* srv, const gace_request* req, uint64
 /* Wait until request `ticket` is done (timeout_ns < 0: forever).  Its status
    goes to *req_status; GACE_ETIMEOUT if still running. */
 gace_status gace_server_wait(gace_server* srv, uint64_t ticket, int64_t timeout_ns, gace_status* req_status);
+/* As gace_server_wait, and also returns when the request was submitted and
+   when the server saw its batch finish, in nanoseconds of CLOCK_MONOTONIC
+   (either pointer may be NULL).  Latency = done - arrival. */
+gace_status gace_server_wait_times(gace_server* srv, uint64_t ticket, int64_t timeout_ns, gace_status* req_status,
+                                   uint64_t* submit_ns, uint64_t* done_ns);
 gace_status gace_server_stats_get(gace_server* srv, gace_server_stats* out);
 gace_status gace_server_destroy(gace_server* srv);
 

@@ -90,6 +90,11 @@ class gace_trace_rec(ctypes.Structure):
                 ("t_end", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
 
 
+class gace_kernel_stats(ctypes.Structure):
+    _fields_ = [("scan_ms", ctypes.c_double), ("join_ms", ctypes.c_double), ("scan_alg_bytes", ctypes.c_uint64),
+                ("join_alg_bytes", ctypes.c_uint64), ("timed", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class gace_server_cfg(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
                 ("queue_capacity", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
@@ -104,9 +109,10 @@ class gace_server_stats(ctypes.Structure):
 ABI_FUNCTIONS = [
     "gace_create", "gace_destroy", "gace_last_error", "gace_version", "gace_check_request",
     "gace_probe_selectivity", "gace_join_freq", "gace_batch_run", "gace_autotune", "gace_get_schedule",
-    "gace_set_schedule", "gace_last_batch_stats", "gace_set_trace", "gace_get_trace",
+    "gace_set_schedule", "gace_last_batch_stats", "gace_last_kernel_stats", "gace_set_graph",
+    "gace_set_trace", "gace_get_trace",
     "gace_server_create", "gace_server_submit",
-    "gace_server_wait", "gace_server_stats_get", "gace_server_destroy",
+    "gace_server_wait", "gace_server_wait_times", "gace_server_stats_get", "gace_server_destroy",
 ]
 
 _lib = None
@@ -142,12 +148,16 @@ def lib():
             "gace_set_schedule": ([P, ctypes.POINTER(gace_schedule)], i32),
             "gace_last_batch_stats": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
                                        ctypes.POINTER(u64)], i32),
+            "gace_last_kernel_stats": ([P, ctypes.POINTER(gace_kernel_stats)], i32),
+            "gace_set_graph": ([P, ctypes.c_int], i32),
             "gace_set_trace": ([P, ctypes.c_int], i32),
             "gace_get_trace": ([P, ctypes.POINTER(gace_trace_rec), u32, ctypes.POINTER(u32),
                                 ctypes.POINTER(ctypes.c_double)], i32),
             "gace_server_create": ([ctypes.c_int, ctypes.POINTER(gace_server_cfg), ctypes.POINTER(P)], i32),
             "gace_server_submit": ([P, ctypes.POINTER(gace_request), ctypes.POINTER(u64)], i32),
             "gace_server_wait": ([P, u64, ctypes.c_int64, ctypes.POINTER(i32)], i32),
+            "gace_server_wait_times": ([P, u64, ctypes.c_int64, ctypes.POINTER(i32), ctypes.POINTER(u64),
+                                        ctypes.POINTER(u64)], i32),
             "gace_server_stats_get": ([P, ctypes.POINTER(gace_server_stats)], i32),
             "gace_server_destroy": ([P], i32),
         }
@@ -406,6 +416,17 @@ def gace_last_batch_stats(ctx: int) -> dict:
     return dict(kernel_ms=ms.value, alg_bytes=int(ab.value), rows_preds=int(rp.value))
 
 
+def gace_last_kernel_stats(ctx: int) -> dict:
+    k = gace_kernel_stats()
+    _check(lib().gace_last_kernel_stats(ctx, ctypes.byref(k)))
+    return dict(timed=bool(k.timed), scan_ms=k.scan_ms, join_ms=k.join_ms, scan_alg_bytes=int(k.scan_alg_bytes),
+                join_alg_bytes=int(k.join_alg_bytes))
+
+
+def gace_set_graph(ctx: int, enable: bool = True):
+    _check(lib().gace_set_graph(ctx, 1 if enable else 0))
+
+
 def gace_set_trace(ctx: int, enable: bool = True):
     _check(lib().gace_set_trace(ctx, 1 if enable else 0))
 
@@ -449,6 +470,25 @@ def gace_server_wait(srv: int, ticket: int, timeout_ns: int = -1) -> int:
     st = ctypes.c_int32()
     _check(lib().gace_server_wait(srv, ticket, timeout_ns, ctypes.byref(st)))
     return int(st.value)
+
+
+def gace_server_wait_times(srv: int, ticket: int, timeout_ns: int = -1):
+    """(status, submit_ns, done_ns); times are CLOCK_MONOTONIC nanoseconds, the
+    clock of time.monotonic_ns()."""
+    st = ctypes.c_int32()
+    t0 = ctypes.c_uint64()
+    t1 = ctypes.c_uint64()
+    _check(lib().gace_server_wait_times(srv, ticket, timeout_ns, ctypes.byref(st), ctypes.byref(t0),
+                                        ctypes.byref(t1)))
+    return int(st.value), int(t0.value), int(t1.value)
+
+
+def gace_server_submit_raw(srv: int, req_ptr) -> int:
+    """Submit a request already marshalled as a gace_request (pointer or
+    byref); the caller keeps its arrays alive until it completes."""
+    t = ctypes.c_uint64()
+    _check(lib().gace_server_submit(srv, req_ptr, ctypes.byref(t)))
+    return int(t.value)
 
 
 def gace_server_stats_get(srv: int) -> dict:

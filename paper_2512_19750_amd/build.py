@@ -15,10 +15,20 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-shared", "-std=c++17", "-Wal
          "-I" + os.path.join(ROOT, "include"), "-lpthread"]
 
 
+def source_hash() -> str:
+    """Hash of every library source: names the kernels a tuned schedule was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(HERE, "csrc"))):
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(HERE, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
+    cmd = [HIPCC, *FLAGS, '-DGACE_SOURCE_HASH="%s"' % source_hash(), "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -13,9 +13,11 @@
 #include "compile.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <tuple>
 
 namespace gace {
@@ -245,23 +247,35 @@ static void build_group(const std::vector<BitRef>& bits, const gace_table* table
 
     std::vector<ColBuild> builds;
     std::vector<Iv> iv;
+    // the term intervals on one column, in (bit, term) order: one flat list
+    // reused across columns (this runs for every group of every batch)
+    struct TermIv {
+        uint32_t bit, term;
+        Iv x;
+    };
+    std::vector<TermIv> tiv;
+    std::vector<u128> B;
+    std::vector<uint32_t> nterm(nb);
+    std::vector<uint8_t> acc, tacc;
     for (uint32_t col : refcols) {
         const uint32_t dt = table->cols[col].dtype;
         const bool wide = dt == GACE_I64;
         const u128 END = wide ? ((u128)1 << 64) : ((u128)1 << 32);
-        // per bit: the term intervals on this column
-        std::vector<std::vector<std::vector<Iv>>> per_bit(nb);
-        std::vector<u128> B;
-        for (uint32_t i = 0; i < nb; ++i)
+        tiv.clear();
+        B.clear();
+        for (uint32_t i = 0; i < nb; ++i) {
+            nterm[i] = 0;
             for (uint32_t t = 0; t < bits[i].n_terms; ++t)
                 if (bits[i].terms[t].col == col) {
                     term_intervals(dt, bits[i].terms[t], iv);
                     for (const Iv& x : iv) {
                         if (x.a > 0) B.push_back(x.a);
                         if (x.b < END) B.push_back(x.b);
+                        tiv.push_back({i, nterm[i], x});
                     }
-                    per_bit[i].push_back(iv);
+                    ++nterm[i];
                 }
+        }
         std::sort(B.begin(), B.end());
         B.erase(std::unique(B.begin(), B.end()), B.end());
         const uint32_t m = (uint32_t)B.size();
@@ -273,23 +287,26 @@ static void build_group(const std::vector<BitRef>& bits, const gace_table* table
         std::vector<uint64_t> mask(m + 1, 0);
         std::vector<uint64_t> diff(m + 2, 0);
         uint64_t no_term = 0;
-        std::vector<uint8_t> acc, tacc;
+        size_t e = 0;   // cursor into tiv
         for (uint32_t i = 0; i < nb; ++i) {
             const uint64_t bit = 1ull << i;
-            if (per_bit[i].empty()) { no_term |= bit; continue; }
-            if (per_bit[i].size() == 1) {
-                for (const Iv& x : per_bit[i][0]) {
-                    diff[idx(x.a)] ^= bit;
-                    diff[idx(x.b)] ^= bit;
+            if (nterm[i] == 0) { no_term |= bit; continue; }
+            const size_t e0 = e;
+            while (e < tiv.size() && tiv[e].bit == i) ++e;
+            if (nterm[i] == 1) {
+                for (size_t k = e0; k < e; ++k) {
+                    diff[idx(tiv[k].x.a)] ^= bit;
+                    diff[idx(tiv[k].x.b)] ^= bit;
                 }
                 continue;
             }
             acc.assign(m + 1, 1);
-            for (const auto& term : per_bit[i]) {
+            for (size_t k = e0; k < e;) {
+                const uint32_t t = tiv[k].term;
                 tacc.assign(m + 2, 0);
-                for (const Iv& x : term) {
-                    tacc[idx(x.a)] ^= 1;
-                    tacc[idx(x.b)] ^= 1;
+                for (; k < e && tiv[k].term == t; ++k) {
+                    tacc[idx(tiv[k].x.a)] ^= 1;
+                    tacc[idx(tiv[k].x.b)] ^= 1;
                 }
                 uint8_t run = 0;
                 for (uint32_t j = 0; j <= m; ++j) {
@@ -297,6 +314,11 @@ static void build_group(const std::vector<BitRef>& bits, const gace_table* table
                     acc[j] &= run;
                 }
             }
+            // a term with no interval on the line (an empty range) accepts nothing
+            uint32_t seen_terms = 0;
+            for (size_t k = e0; k < e; ++k)
+                if (k == e0 || tiv[k].term != tiv[k - 1].term) ++seen_terms;
+            if (seen_terms < nterm[i]) acc.assign(m + 1, 0);
             for (uint32_t j = 0; j <= m; ++j)
                 if (acc[j]) mask[j] |= bit;
         }
@@ -452,6 +474,14 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     std::vector<uint64_t> rthr;
     std::vector<uint32_t> rcum;
     std::vector<std::vector<uint8_t>> tabs;
+    struct GroupJob {
+        std::vector<BitRef> bits;
+        const gace_table* table;
+        GroupDesc G;
+        std::vector<ColProg> cols;
+        std::vector<uint8_t> tab;
+    };
+    std::vector<GroupJob> jobs;
     uint32_t n_counts = 0, n_hist = 0;
     for (uint32_t s = 0; s < scan_reqs.size(); ++s) {
         auto& sr = scan_reqs[s];
@@ -469,7 +499,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         S.n_req = (uint32_t)sr.size();
         S.hist_off = n_hist;
         n_hist += 2 * (S.n_req + 1);
-        S.group_begin = (uint32_t)groups.size();
+        S.group_begin = (uint32_t)jobs.size();
 
         std::vector<BitRef> bits;
         std::vector<uint32_t> bit_slot;
@@ -503,18 +533,39 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
 
         for (uint32_t g0 = 0; g0 < bits.size(); g0 += 64) {
             const uint32_t g1 = std::min<uint32_t>((uint32_t)bits.size(), g0 + 64);
-            std::vector<BitRef> gb(bits.begin() + g0, bits.begin() + g1);
-            GroupDesc G;
-            std::memset(&G, 0, sizeof(G));
-            std::vector<uint8_t> tab;
-            build_group(gb, &r0.table, G, cols, tab);
-            G.slot_index = (uint32_t)slots.size();
+            GroupJob job;
+            job.bits.assign(bits.begin() + g0, bits.begin() + g1);
+            job.table = &r0.table;
+            std::memset(&job.G, 0, sizeof(job.G));
+            job.G.slot_index = (uint32_t)slots.size();
             for (uint32_t i = g0; i < g0 + 64; ++i) slots.push_back(i < g1 ? bit_slot[i] : 0);
-            groups.push_back(G);
-            tabs.push_back(std::move(tab));
+            jobs.push_back(std::move(job));
         }
-        S.n_groups = (uint32_t)groups.size() - S.group_begin;
+        S.n_groups = (uint32_t)jobs.size() - S.group_begin;
         scans.push_back(S);
+    }
+    // the groups compile independently: spread them over a few host threads,
+    // then append their column programs and tables in group order
+    {
+        std::atomic<uint32_t> next{0};
+        auto work = [&] {
+            for (uint32_t j; (j = next.fetch_add(1)) < jobs.size();)
+                build_group(jobs[j].bits, jobs[j].table, jobs[j].G, jobs[j].cols, jobs[j].tab);
+        };
+        const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
+        const uint32_t nt = std::min<uint32_t>({hw, 16u, (uint32_t)(jobs.size() + 7) / 8});
+        std::vector<std::thread> pool;
+        for (uint32_t t = 1; t < nt; ++t) pool.emplace_back(work);
+        work();
+        for (auto& t : pool) t.join();
+        for (GroupJob& job : jobs) {
+            GroupDesc G = job.G;
+            G.col_begin += (uint32_t)cols.size();
+            G.col_end += (uint32_t)cols.size();
+            cols.insert(cols.end(), job.cols.begin(), job.cols.end());
+            groups.push_back(G);
+            tabs.push_back(std::move(job.tab));
+        }
     }
     // the reqcum array interleaves per scan: entries [req_begin + scan_index, ...) -- keep it simple by
     // rebuilding it with explicit per-scan offsets
@@ -542,7 +593,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
 
     // ---- joins: hash-partitioned key aggregation
     std::vector<JoinDesc> joins;
-    std::vector<Item> hist_items, off_items, base_items, scatter_items, agg_items;
+    std::vector<Item> hist_items, off_items, base_items, scatter_items, scatter2_items, agg_items;
     uint64_t arena_static = 0;
     auto carve = [&](uint64_t bytes) {
         const uint64_t off = arena_static;
@@ -554,9 +605,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         JoinDesc J;
         std::memset(&J, 0, sizeof(J));
         const gace_keys* sides[2] = {&r.R, &r.S};
-        double expect = 0.0;
-        uint32_t item = 0;
-        std::vector<Item> my_items;
+        double expect = 0.0, side_p[2];
         for (uint32_t sd = 0; sd < 2; ++sd) {
             JoinSide& D = J.side[sd];
             D.keys = sides[sd]->keys;
@@ -566,25 +615,50 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
             D.log2B = log2u(sides[sd]->spec.block_rows);
             D.n_blocks = (D.n + (1ull << D.log2B) - 1) >> D.log2B;
             D.table_id = sides[sd]->table_id;
-            D.item_begin = item;
-            const double p = D.thr >= kThrAll ? 1.0 : (double)D.thr / 4294967296.0;
-            expect += (double)D.n * p;
-            const uint64_t bb = bpi_for(D.thr, D.log2B, opt.item_rows);
-            if (bb && D.n)
-                for (uint64_t b = 0; b < D.n_blocks; b += bb) {
-                    Item it = {IT_JHIST, j, sd, item++, b, std::min(D.n_blocks, b + bb)};
-                    my_items.push_back(it);
-                }
-            D.n_items = item - D.item_begin;
+            side_p[sd] = D.thr >= kThrAll ? 1.0 : (double)D.thr / 4294967296.0;
+            expect += (double)D.n * side_p[sd];
         }
         uint32_t log2P = 0;
         while (log2P < kPartBitsMax && (double)(1u << log2P) * (double)opt.join_part_keys < expect) ++log2P;
         const uint32_t P = 1u << log2P;
+        // two passes when the fan-out is too wide for one LDS-staged pass:
+        // first 2^log2P1 buckets, then 2^log2P2 partitions inside each bucket
+        const uint32_t log2P2 = log2P > 6 ? log2P / 2 : 0;
+        const uint32_t log2P1 = log2P - log2P2;
+        // items large enough that the per-item partition counts (4 P bytes)
+        // stay small next to the item's keys
+        const uint32_t item_keys = std::max<uint32_t>(opt.item_rows, 32u * P);
+        uint32_t item = 0;
+        std::vector<Item> my_items;
+        double keys_per_item = 1.0;
+        for (uint32_t sd = 0; sd < 2; ++sd) {
+            JoinSide& D = J.side[sd];
+            D.item_begin = item;
+            const uint64_t bb = bpi_for(D.thr, D.log2B, item_keys);
+            if (bb && D.n) {
+                for (uint64_t b = 0; b < D.n_blocks; b += bb) {
+                    Item it = {IT_JHIST, j, sd, item++, b, std::min(D.n_blocks, b + bb)};
+                    my_items.push_back(it);
+                }
+                keys_per_item = std::max(keys_per_item, (double)bb * (double)(1ull << D.log2B) * side_p[sd]);
+            }
+            D.n_items = item - D.item_begin;
+        }
         J.log2P = log2P;
+        J.log2P2 = log2P2;
         J.acc = j;
         J.n_items = item;
         J.n_off = (P + 63) / 64;
         J.n_agg = std::min<uint32_t>(512, std::max<uint32_t>(1, (P + 15) / 16));
+        if (log2P2) {
+            // second-pass unit: one first-pass bucket of a group of items
+            const double g = (double)kUnit2Keys * (double)(1u << log2P1) / keys_per_item;
+            J.group_items = (uint32_t)std::min(1e6, std::max(1.0, g));
+            for (uint32_t sd = 0; sd < 2; ++sd)
+                J.n_groups[sd] = (J.side[sd].n_items + J.group_items - 1) / J.group_items;
+            J.n_units2 = (J.n_groups[0] + J.n_groups[1]) << log2P1;
+            J.n_s2 = std::min<uint32_t>(512, std::max<uint32_t>(1, J.n_units2 / 4));
+        }
         J.rows_off = carve((uint64_t)item * P * 4);
         J.base_off = carve(2ull * (P + 1) * 4);
         J.stats_off = carve((uint64_t)item * 16);
@@ -605,6 +679,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         }
         for (uint32_t c = 0; c < J.n_off; ++c) off_items.push_back({IT_JOFF, j, 0, c, 0, 0});
         base_items.push_back({IT_JBASE, j, 0, 0, 0, 0});
+        for (uint32_t w = 0; w < J.n_s2; ++w) scatter2_items.push_back({IT_JSCATTER2, j, 0, w, 0, 0});
         for (uint32_t w = 0; w < J.n_agg; ++w) agg_items.push_back({IT_JAGG, j, 0, w, 0, 0});
         joins.push_back(J);
         JoinOut jo;
@@ -632,7 +707,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     // join item only ever waits for items earlier in its queue
     out.items.insert(out.items.end(), scan_items.begin(), scan_items.end());
     const uint32_t n_scan_items = (uint32_t)out.items.size();
-    for (auto* v : {&hist_items, &off_items, &base_items, &scatter_items, &agg_items})
+    for (auto* v : {&hist_items, &off_items, &base_items, &scatter_items, &scatter2_items, &agg_items})
         out.items.insert(out.items.end(), v->begin(), v->end());
 
     // ---- plan blob
@@ -648,6 +723,13 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     H.n_scan_items = n_scan_items;
     H.arena_static = arena_static;
     std::vector<uint8_t>& blob = out.plan;
+    {
+        size_t est = sizeof(PlanHdr) + 16 * 16 + scans.size() * sizeof(ScanDesc) + groups.size() * sizeof(GroupDesc) +
+                     cols.size() * sizeof(ColProg) + slots.size() * 4 + rthr_flat.size() * 8 + rcum_flat.size() * 4 +
+                     joins.size() * sizeof(JoinDesc);
+        for (const auto& t : tabs) est += t.size() + 16;
+        blob.reserve(est);
+    }
     blob.assign(sizeof(PlanHdr), 0);
     auto put = [&](const void* p, size_t nbytes) -> uint32_t {
         const uint32_t off = align_up((uint32_t)blob.size(), 16);

@@ -30,7 +30,12 @@ constexpr uint32_t kLdsCnt = kScanLdsGroups * 64 * 4;
 constexpr uint32_t kLdsHist = kScanLdsHist * 2 * 8;
 constexpr uint32_t kLdsThr = kScanLdsHist * 8 + 640;                             // thresholds + bit prefix sums
 constexpr uint32_t kLdsBytes = kLdsMisc + kLdsCnt + kLdsHist + kLdsThr + kGroupTabBudget;   // scan kernel
-constexpr uint32_t kJoinLdsBytes = kLdsMisc + 8192 * 4 + 512;                      // join kernel
+constexpr int kPer = kTileKeys / kWG;                                              // staged keys per thread
+constexpr uint32_t kTileLdsBytes = 3 * 132 * 4 + kTileKeys * 8 + kTileKeys;          // cursors, counts, starts, tile
+constexpr uint32_t kAggLdsBytes = kAggSlots * 16 + 512;                             // key table + split stack
+constexpr uint32_t kJoinLdsBytes =
+    kLdsMisc + (kTileLdsBytes > kAggLdsBytes ? (kTileLdsBytes > 8192 * 4 ? kTileLdsBytes : 8192 * 4)
+                                             : (kAggLdsBytes > 8192 * 4 ? kAggLdsBytes : 8192 * 4));
 
 // explicit address spaces: pointers read from the plan are generic to the
 // compiler; global loads through them must not become flat loads, which would
@@ -239,6 +244,7 @@ __device__ __forceinline__ void lookup64(const ColProg& P, const uint8_t* tab, u
 // tiles of 4096 rows over a set of kept blocks of one 64-block chunk
 struct TileIt {
     uint64_t start, end;        // tile start row, end row of its block
+    uint32_t j;                 // the block's index in the chunk
 };
 
 __device__ __forceinline__ bool tile_first(TileIt& t, unsigned long long& rest, uint64_t cb, uint64_t B,
@@ -248,7 +254,16 @@ __device__ __forceinline__ bool tile_first(TileIt& t, unsigned long long& rest, 
     rest &= rest - 1;
     t.start = (cb + (uint64_t)j) * B;
     t.end = t.start + B < n ? t.start + B : n;
+    t.j = (uint32_t)j;
     return true;
+}
+
+// predicate bits of group g active for a block whose requests own the first
+// act_bits predicate bits of the scan
+__device__ __forceinline__ uint64_t group_prefix(uint32_t act_bits, uint32_t g) {
+    if (act_bits <= g * 64) return 0ull;
+    const uint32_t na = act_bits - g * 64;
+    return na >= 64 ? ~0ull : ((1ull << na) - 1ull);
 }
 
 __device__ __forceinline__ bool tile_next(TileIt& t, unsigned long long& rest, uint64_t cb, uint64_t B,
@@ -258,17 +273,18 @@ __device__ __forceinline__ bool tile_next(TileIt& t, unsigned long long& rest, u
     return tile_first(t, rest, cb, B, n);
 }
 
-// all rows of the blocks in `blocks` (bit j = block cb + j) for one group.
-// The 32-bit column loads of the next column -- or of the next tile's first
-// column after the last one -- are issued before the current column's
-// lookups, so each lane keeps 4-8 loads of 16 B in flight across the whole
-// block set.  tab points at the group's masks/boundaries in address space AS
-// (LDS when staged, else global).
+// all rows of the blocks in `blocks` (bit j = block cb + j) for group g: a
+// block's active predicates are the group's bits among the first s_act[j]
+// predicate bits of the scan.  The 32-bit column loads of the next column --
+// or of the next tile's first column after the last one -- are issued before
+// the current column's lookups, so each lane keeps 4-8 loads of 16 B in
+// flight across all the blocks.  tab points at the group's masks/boundaries
+// in address space AS (LDS when staged, else global).
 template <int AS>
 __device__ __forceinline__ uint32_t scan_blocks(const ColProg* cols, uint32_t c_begin, uint32_t c_end,
                                                 const uint8_t* tab, unsigned long long blocks, uint64_t cb,
-                                                uint64_t B, uint64_t n, uint64_t active, int lane, int wave,
-                                                uint32_t mode) {
+                                                uint64_t B, uint64_t n, uint64_t base_mask, const uint32_t* s_act,
+                                                uint32_t g, int lane, int wave, uint32_t mode) {
     uint32_t cnt = 0;
     uint32_t first32 = c_begin;
     while (first32 < c_end && cols[first32].kind == CP_RANK64) ++first32;
@@ -285,6 +301,7 @@ __device__ __forceinline__ uint32_t scan_blocks(const ColProg* cols, uint32_t c_
         TileIt tn = t;
         unsigned long long rest_n = rest;
         const bool has_next = tile_next(tn, rest_n, cb, B, n);
+        const uint64_t active = base_mask & group_prefix(s_act[t.j], g);
         uint64_t m[kRows];
 #pragma unroll
         for (int i = 0; i < kRows; ++i) m[i] = active;
@@ -347,6 +364,7 @@ __device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, 
     unsigned long long* s_keep = (unsigned long long*)(lds + 256);
     int* s_staged = (int*)(lds + 264);
     uint32_t* s_k = (uint32_t*)(lds + 384);
+    uint32_t* s_act = s_w0;   // per block: predicate bits its requests own (replaces w0 once k is known)
     uint32_t* s_cnt = (uint32_t*)(lds + kLdsMisc);
     unsigned long long* s_hist = (unsigned long long*)(lds + kLdsMisc + kLdsCnt);
     uint64_t* s_thr = (uint64_t*)(lds + kLdsMisc + kLdsCnt + kLdsHist);
@@ -380,6 +398,7 @@ __device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, 
             for (uint32_t step = 1u << 31; step; step >>= 1)
                 if (k + step <= S.n_req && (small ? s_thr[k + step - 1] : rthr[k + step - 1]) > w0) k += step;
             s_k[threadIdx.x] = k;
+            s_act[threadIdx.x] = small ? s_cum[k] : rcum[k];
             const uint64_t r0 = (cb + threadIdx.x) * B;
             const uint64_t rows = (r0 + B < S.n_rows ? r0 + B : S.n_rows) - r0;
             if (small) {
@@ -391,18 +410,13 @@ __device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, 
             }
         }
         __syncthreads();
-        // blocks with the same k share their active predicates: stream them together
-        unsigned long long rest = keep;
-        while (rest) {
-            const uint32_t k0 = s_k[__ffsll((long long)rest) - 1];
-            const unsigned long long same = __ballot(((rest >> lane) & 1ull) && s_k[lane] == k0);
-            rest &= ~same;
-            const uint32_t act_bits = small ? s_cum[k0] : rcum[k0];
-            for (uint32_t g = 0; g * 64 < act_bits; ++g) {
+        // group-major: group g streams every kept block whose requests reach
+        // into it, each block with its own active bits
+        {
+            for (uint32_t g = 0;; ++g) {
+                const unsigned long long blocks_g = __ballot(((keep >> lane) & 1ull) && s_act[lane] > g * 64);
+                if (!blocks_g) break;
                 const GroupDesc G = groups[g];
-                const uint32_t na = act_bits - g * 64;
-                const uint64_t active = G.base_mask & (na >= 64 ? ~0ull : ((1ull << na) - 1));
-                if (active == 0) continue;
                 uint32_t cnt;
                 if (G.tab_bytes <= kGroupTabBudget) {
                     if (*s_staged != (int)g) {
@@ -413,11 +427,11 @@ __device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, 
                         __syncthreads();
                         if (threadIdx.x == 0) *s_staged = (int)g;
                     }
-                    cnt = scan_blocks<3>(cols, G.col_begin, G.col_end, s_tab, same, cb, B, S.n_rows, active, lane,
-                                         wave, a.count_mode);
+                    cnt = scan_blocks<3>(cols, G.col_begin, G.col_end, s_tab, blocks_g, cb, B, S.n_rows,
+                                         G.base_mask, s_act, g, lane, wave, a.count_mode);
                 } else {
-                    cnt = scan_blocks<1>(cols, G.col_begin, G.col_end, a.plan + G.tab_off, same, cb, B, S.n_rows,
-                                         active, lane, wave, a.count_mode);
+                    cnt = scan_blocks<1>(cols, G.col_begin, G.col_end, a.plan + G.tab_off, blocks_g, cb, B,
+                                         S.n_rows, G.base_mask, s_act, g, lane, wave, a.count_mode);
                 }
                 if (cnt) {
                     if (g < n_lds_groups) atomicAdd(&s_cnt[g * 64 + lane], cnt);
@@ -473,7 +487,7 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, un
     return t;
 }
 
-// calls f(key) for every sampled key of blocks [b0, b1) of one side; four
+// calls f(key) for every sampled key of blocks [b0, b1) of one side; eight
 // loads per thread are issued before use
 template <typename F>
 __device__ __forceinline__ void for_each_sampled_key(const JoinSide* D, uint64_t b0, uint64_t b1, uint8_t* lds,
@@ -491,15 +505,15 @@ __device__ __forceinline__ void for_each_sampled_key(const JoinSide* D, uint64_t
             keep &= keep - 1;
             const uint64_t r0 = (cb + (uint64_t)j) * B;
             const uint64_t r1 = (r0 + B < n) ? r0 + B : n;
-            for (uint64_t r = r0 + threadIdx.x; r < r1; r += 4 * kWG) {
-                uint64_t k[4];
+            for (uint64_t r = r0 + threadIdx.x; r < r1; r += 8 * kWG) {
+                uint64_t k[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
                     const uint64_t rr = r + (uint64_t)u * kWG;
                     k[u] = rr < r1 ? (uint64_t)__builtin_nontemporal_load(keys + rr) : 0ull;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 8; ++u)
                     if (r + (uint64_t)u * kWG < r1) f(k[u]);
             }
         }
@@ -708,46 +722,270 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
         acc.nkeys[1] = tot[1];
         acc.n_units = (uint32_t)(t_chunk + t_small + t_split);
         const unsigned long long kbytes = 8ull * (tot[0] + tot[1]);
+        const unsigned long long tbytes = jd->log2P2 ? kbytes : 0ull;
         const unsigned long long mbytes = t_chunk * (unsigned long long)kChunkKeys * sizeof(MergeEntry);
-        const unsigned long long off = atomicAdd(&a.arena->used, kbytes + mbytes);
-        if (!fits || off + kbytes + mbytes > a.arena->size) acc.status = 2;
+        const unsigned long long off = atomicAdd(&a.arena->used, kbytes + tbytes + mbytes);
+        if (!fits || off + kbytes + tbytes + mbytes > a.arena->size) acc.status = 2;
         acc.buf_off = off;
-        acc.merge_off = off + kbytes;
+        acc.tmp_off = off + kbytes;
+        acc.merge_off = off + kbytes + tbytes;
     }
 }
 
+// ---- LDS-staged partitioning
+// A tile of up to kTileKeys keys is counting-sorted by digit in LDS and each
+// digit's run is written to its output cursor with consecutive lanes on
+// consecutive addresses, so the partition writes are whole cache lines
+// instead of one scattered 8-byte store per key.
+struct TileLds {
+    uint32_t* cur;               // [F] output cursor per digit (keys from the side's buffer start)
+    uint32_t* cnt;               // [F] tile count per digit
+    uint32_t* start;             // [F + 1] tile start per digit; start[F] = keys in the tile
+    unsigned long long* key;     // [kTileKeys] keys sorted by digit
+    uint8_t* dig;                // [kTileKeys] their digits
+};
+
+__device__ __forceinline__ TileLds tile_lds(uint8_t* lds) {
+    TileLds L;
+    L.cur = (uint32_t*)(lds + kLdsMisc);
+    L.cnt = L.cur + 132;
+    L.start = L.cnt + 132;
+    L.key = (unsigned long long*)(lds + kLdsMisc + 3 * 132 * 4);
+    L.dig = (uint8_t*)(L.key + kTileKeys);
+    return L;
+}
+
+// digit of a key: (hash >> shift) mod F (F a power of two <= 128)
+__device__ void tile_partition(const uint64_t (&k)[kPer], uint32_t nt, uint32_t shift, uint32_t F,
+                               GACE_GLOBAL int64_t* dst, const TileLds& L) {
+    for (uint32_t i = threadIdx.x; i < F; i += kWG) L.cnt[i] = 0;
+    __syncthreads();
+    uint32_t rd[kPer];   // rank in its digit << 8 | digit, or ~0 for no key
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const uint32_t pos = threadIdx.x + (uint32_t)u * kWG;
+        rd[u] = ~0u;
+        if (pos < nt && k[u] != kEmptyKey) {
+            const uint32_t d = F > 1 ? (uint32_t)(mix_key(k[u]) >> shift) & (F - 1) : 0u;
+            rd[u] = atomicAdd(&L.cnt[d], 1u) << 8 | d;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t lane = threadIdx.x;
+        const uint32_t a0 = 2 * lane < F ? L.cnt[2 * lane] : 0u;
+        const uint32_t a1 = 2 * lane + 1 < F ? L.cnt[2 * lane + 1] : 0u;
+        uint32_t x = a0 + a1;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if ((int)lane >= o) x += y;
+        }
+        const uint32_t ex = x - a0 - a1;
+        if (2 * lane < F) L.start[2 * lane] = ex;
+        if (2 * lane + 1 < F) L.start[2 * lane + 1] = ex + a0;
+        if (lane == 63) L.start[F] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        if (rd[u] != ~0u) {
+            const uint32_t d = rd[u] & 0xFFu;
+            const uint32_t at = L.start[d] + (rd[u] >> 8);
+            L.key[at] = k[u];
+            L.dig[at] = (uint8_t)d;
+        }
+    }
+    __syncthreads();
+    const uint32_t m = L.start[F];
+    for (uint32_t i = threadIdx.x; i < m; i += kWG) {
+        const uint32_t dd = L.dig[i];
+        dst[(uint64_t)L.cur[dd] + (i - L.start[dd])] = (int64_t)L.key[i];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < F; i += kWG) L.cur[i] += L.cnt[i];
+    __syncthreads();
+}
+
+// calls f(k, nt) for consecutive tiles of the sampled keys of blocks [b0, b1)
+// of one side: tile position t (thread + u * kWG) holds k[u] when t < nt.
+// Tiles run over the concatenated rows of the kept blocks of each 64-block
+// decision chunk, so small blocks still fill whole tiles.
+template <typename F>
+__device__ void for_each_tile(const JoinSide* D, uint64_t b0, uint64_t b1, uint8_t* lds, F&& f) {
+    uint32_t* s_w0 = (uint32_t*)lds;
+    unsigned long long* s_keep = (unsigned long long*)(lds + 256);
+    uint32_t* s_kidx = (uint32_t*)(lds + 384);
+    const uint32_t log2B = D->log2B;
+    const uint64_t B = 1ull << log2B, n = D->n;
+    const GACE_GLOBAL int64_t* keys = (const GACE_GLOBAL int64_t*)D->keys;
+    for (uint64_t cb = b0; cb < b1; cb += 64) {
+        decide_blocks(cb, b1, D->thr, D->table_id, D->seed, s_w0, s_keep);
+        __syncthreads();
+        const unsigned long long keep = *s_keep;
+        if (threadIdx.x < 64 && ((keep >> threadIdx.x) & 1ull))
+            s_kidx[__popcll(keep & ((1ull << threadIdx.x) - 1ull))] = threadIdx.x;
+        __syncthreads();
+        const uint32_t c = (uint32_t)__popcll(keep);
+        if (c) {
+            // only the side's final block can be short, and it is the chunk's last kept block
+            const uint64_t last = (cb + s_kidx[c - 1]) << log2B;
+            const uint64_t total = (uint64_t)(c - 1) * B + min(B, n - last);
+            // the next tile's keys are loaded while this tile is partitioned
+            auto load = [&](uint64_t t0, uint64_t (&k)[kPer]) {
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) {
+                    const uint64_t pos = t0 + threadIdx.x + (uint64_t)u * kWG;
+                    k[u] = 0;
+                    if (pos < total) {
+                        const uint64_t row = ((cb + s_kidx[pos >> log2B]) << log2B) + (pos & (B - 1));
+                        k[u] = (uint64_t)__builtin_nontemporal_load(keys + row);
+                    }
+                }
+            };
+            uint64_t k[kPer], kn[kPer];
+            load(0, k);
+            for (uint64_t t0 = 0; t0 < total; t0 += kTileKeys) {
+                const uint32_t nt = (uint32_t)min((uint64_t)kTileKeys, total - t0);
+                const bool more = t0 + kTileKeys < total;
+                if (more) load(t0 + kTileKeys, kn);
+                f(k, nt);
+                if (more) {
+#pragma unroll
+                    for (int u = 0; u < kPer; ++u) k[u] = kn[u];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// first pass: each item's keys go to their first-pass bucket (top log2P1
+// hash bits) in the temporary buffer, or straight to their partition when one
+// pass suffices.  An item's run inside a bucket starts at the sum of its
+// offsets in the bucket's partitions, so both passes place keys in item order.
 __device__ void jscatter_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds) {
     JoinAcc& acc = a.accs[jd->acc];
-    const uint32_t log2P = jd->log2P, P = 1u << log2P;
+    const uint32_t log2P = jd->log2P, P = 1u << log2P, log2P2 = jd->log2P2, log2P1 = log2P - log2P2;
+    const uint32_t F1 = 1u << log2P1;
     const GACE_GLOBAL uint32_t* base =
         (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off) + (uint64_t)it.side * (P + 1);
     const GACE_GLOBAL uint32_t* row = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off) + (uint64_t)it.sub * P;
-    uint32_t* cur = (uint32_t*)(lds + kLdsMisc);
-    for (uint32_t i = threadIdx.x; i < P; i += kWG) cur[i] = base[i] + row[i];
+    const TileLds L = tile_lds(lds);
+    for (uint32_t i = threadIdx.x; i < F1; i += kWG) L.cur[i] = 0;
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < P; p += kWG) atomicAdd(&L.cur[p >> log2P2], row[p]);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < F1; b += kWG) L.cur[b] += base[b << log2P2];
     __syncthreads();
     if (__hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    GACE_GLOBAL int64_t* buf = (GACE_GLOBAL int64_t*)(a.arena_base + acc.buf_off) + (it.side ? acc.nkeys[0] : 0ull);
-    for_each_sampled_key(&jd->side[it.side], it.begin, it.end, lds, [&](uint64_t key) {
-        if (key == kEmptyKey) return;
-        const uint32_t pos = atomicAdd(&cur[part_of(mix_key(key), log2P)], 1u);
-        buf[pos] = (int64_t)key;
-    });
+    GACE_GLOBAL int64_t* dst = (GACE_GLOBAL int64_t*)(a.arena_base + (log2P2 ? acc.tmp_off : acc.buf_off)) +
+                               (it.side ? acc.nkeys[0] : 0ull);
+    const uint32_t shift = 64 - log2P1;
+    for_each_tile(&jd->side[it.side], it.begin, it.end, lds,
+                  [&](const uint64_t (&k)[kPer], uint32_t nt) { tile_partition(k, nt, shift, F1, dst, L); });
 }
 
-// LDS table of one aggregation pass
+// second pass: a unit is one first-pass bucket of a group of consecutive
+// items of one side; its keys are contiguous in the temporary buffer and are
+// partitioned by the next log2P2 hash bits into their final partitions, where
+// the group's run starts at the first item's offsets
+__device__ void jscatter2_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds) {
+    JoinAcc& acc = a.accs[jd->acc];
+    const uint32_t log2P = jd->log2P, P = 1u << log2P, log2P2 = jd->log2P2, log2P1 = log2P - log2P2;
+    const uint32_t F1 = 1u << log2P1, F2 = 1u << log2P2;
+    const GACE_GLOBAL uint32_t* rows = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off);
+    uint32_t* s_ctl = (uint32_t*)(lds + 352);
+    const TileLds L = tile_lds(lds);
+    if (__hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const uint32_t units0 = jd->n_groups[0] << log2P1;
+    const uint32_t shift = 64 - log2P;
+    for (;;) {
+        if (threadIdx.x == 0) s_ctl[2] = atomicAdd(&acc.next_s2, 1u);
+        __syncthreads();
+        const uint32_t u = s_ctl[2];
+        __syncthreads();
+        if (u >= jd->n_units2) break;
+        const uint32_t side = u >= units0 ? 1u : 0u;
+        const uint32_t uu = side ? u - units0 : u;
+        const uint32_t g = uu >> log2P1, b = uu & (F1 - 1);
+        const JoinSide& D = jd->side[side];
+        const uint32_t i0 = D.item_begin + g * jd->group_items;
+        const uint32_t iend = D.item_begin + D.n_items;
+        const uint32_t i1 = min(iend, i0 + jd->group_items);
+        const GACE_GLOBAL uint32_t* base = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off) +
+                                           (uint64_t)side * (P + 1);
+        const uint32_t p0 = b << log2P2;
+        if (threadIdx.x < 64) {
+            const uint32_t q = threadIdx.x;
+            uint32_t o0 = 0, o1 = 0;
+            if (q < F2) {
+                o0 = rows[(uint64_t)i0 * P + p0 + q];
+                o1 = i1 < iend ? rows[(uint64_t)i1 * P + p0 + q] : base[p0 + q + 1] - base[p0 + q];
+                L.cur[q] = base[p0 + q] + o0;
+            }
+            for (int o = 32; o; o >>= 1) {
+                o0 += __shfl_xor(o0, o);
+                o1 += __shfl_xor(o1, o);
+            }
+            if (q == 0) {
+                s_ctl[4] = o0;
+                s_ctl[5] = o1;
+            }
+        }
+        __syncthreads();
+        const uint64_t side_off = side ? acc.nkeys[0] : 0ull;
+        const GACE_GLOBAL int64_t* src = (const GACE_GLOBAL int64_t*)(a.arena_base + acc.tmp_off) + side_off;
+        GACE_GLOBAL int64_t* dst = (GACE_GLOBAL int64_t*)(a.arena_base + acc.buf_off) + side_off;
+        const uint64_t lo = (uint64_t)base[p0] + s_ctl[4], hi = (uint64_t)base[p0] + s_ctl[5];
+        __syncthreads();
+        auto load = [&](uint64_t t0, uint64_t (&k)[kPer]) {
+#pragma unroll
+            for (int u2 = 0; u2 < kPer; ++u2) {
+                const uint64_t pos = t0 + threadIdx.x + (uint64_t)u2 * kWG;
+                k[u2] = pos < hi ? (uint64_t)__builtin_nontemporal_load(src + pos) : 0ull;
+            }
+        };
+        uint64_t k[kPer], kn[kPer];
+        if (lo < hi) load(lo, k);
+        for (uint64_t t0 = lo; t0 < hi; t0 += kTileKeys) {
+            const uint32_t nt = (uint32_t)min((uint64_t)kTileKeys, hi - t0);
+            const bool more = t0 + kTileKeys < hi;
+            if (more) load(t0 + kTileKeys, kn);
+            tile_partition(k, nt, shift, F2, dst, L);
+            if (more) {
+#pragma unroll
+                for (int u2 = 0; u2 < kPer; ++u2) k[u2] = kn[u2];
+            }
+        }
+    }
+}
+
+// LDS table of one aggregation pass: `slots` (a power of two) entries of
+// which at most `limit` (3/4) may be claimed
 struct AggLds {
     unsigned long long* key;
     uint32_t* c0;
     uint32_t* c1;
+    uint32_t slots, limit;
 };
+
+// table size for a unit of n entries: a power of two with n <= 3/4 of it when
+// it fits, so a unit of at most 3/4 kAggSlots entries never overflows
+__device__ __forceinline__ void agg_size(AggLds& T, uint64_t n) {
+    uint32_t s = kAggMinSlots;
+    while (s < kAggSlots && (uint64_t)s * 3 < n * 4) s <<= 1;
+    T.slots = s;
+    T.limit = s / 4 * 3;
+}
 
 __device__ __forceinline__ void agg_insert(AggLds& T, uint64_t h, uint64_t key, uint32_t c0, uint32_t c1,
                                            uint32_t* s_claims, uint32_t* s_over) {
-    uint32_t i = (uint32_t)(h >> 20) & (kAggSlots - 1);
-    for (uint32_t probe = 0; probe < kAggSlots; ++probe) {
+    const uint32_t mask = T.slots - 1;
+    uint32_t i = (uint32_t)(h >> 20) & mask;
+    for (uint32_t probe = 0; probe < T.slots; ++probe) {
         unsigned long long k = T.key[i];
         if (k == kEmptyKey) {
-            if (atomicAdd(s_claims, 1u) >= kAggLimit) {
+            if (atomicAdd(s_claims, 1u) >= T.limit) {
                 *s_over = 1;
                 return;
             }
@@ -759,7 +997,7 @@ __device__ __forceinline__ void agg_insert(AggLds& T, uint64_t h, uint64_t key, 
             if (c1) atomicAdd(&T.c1[i], c1);
             return;
         }
-        i = (i + 1) & (kAggSlots - 1);
+        i = (i + 1) & mask;
     }
     *s_over = 1;
 }
@@ -773,56 +1011,77 @@ struct AggSeg {
     int side;
 };
 
-// insert the segment's entries whose hash lies in residue class res mod m;
-// the first valid lane's key absorbs its duplicates in the wave (Zipf heads)
+// insert one entry per lane (valid lanes only) whose hash lies in residue
+// class res mod m; the first valid lane's key absorbs its duplicates in the
+// wave (Zipf heads)
+__device__ __forceinline__ void agg_entry(AggLds& T, bool bare, uint64_t key, uint32_t c0, uint32_t c1, bool inr,
+                                          uint64_t m, uint64_t res, uint32_t* s_ctl, int lane) {
+    const uint64_t h = mix_key(key);
+    const bool valid = inr && (h & (m - 1)) == res;
+    const unsigned long long vb = __ballot(valid);
+    if (!vb) return;
+    const int lead = __ffsll((long long)vb) - 1;
+    const uint64_t klead = __shfl(key, lead);
+    const unsigned long long eq = __ballot(valid && key == klead);
+    bool go = valid;
+    const int ne = __popcll(eq);
+    if (ne > 1) {
+        const bool mine = (eq >> lane) & 1ull;
+        uint32_t s0, s1;
+        if (bare) {
+            s0 = c0 ? (uint32_t)ne : 0u;
+            s1 = c1 ? (uint32_t)ne : 0u;
+        } else {
+            s0 = mine ? c0 : 0u;
+            s1 = mine ? c1 : 0u;
+            for (int o = 32; o; o >>= 1) {
+                s0 += __shfl_xor(s0, o);
+                s1 += __shfl_xor(s1, o);
+            }
+        }
+        if (mine) {
+            go = lane == lead;
+            c0 = s0;
+            c1 = s1;
+        }
+    }
+    if (go) agg_insert(T, h, key, c0, c1, &s_ctl[0], &s_ctl[1]);
+}
+
+// insert a segment: each lane loads kAggBatch entries before inserting them,
+// so the loads of a batch are in flight together; stops once the pass has
+// overflowed (it will be redone on split residue classes)
+constexpr int kAggBatch = 4;
 __device__ __forceinline__ void agg_segment(AggLds& T, const AggSeg& sg, uint64_t m, uint64_t res, uint32_t* s_ctl) {
     const int lane = threadIdx.x & 63;
-    for (uint64_t e = threadIdx.x; e - threadIdx.x < sg.n; e += kWG) {
-        const bool inr = e < sg.n;
-        uint64_t key = 0;
-        uint32_t c0 = 0, c1 = 0;
-        if (inr) {
-            if (sg.keys) {
-                key = (uint64_t)sg.keys[e];
-                c0 = sg.side == 0;
-                c1 = sg.side == 1;
-            } else {
-                key = sg.ent[e].key;
-                c0 = sg.ent[e].c0;
-                c1 = sg.ent[e].c1;
-            }
-        }
-        const uint64_t h = mix_key(key);
-        const bool valid = inr && (h & (m - 1)) == res &&
-                           !__hip_atomic_load(&s_ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        const unsigned long long vb = __ballot(valid);
-        if (!vb) continue;
-        const int lead = __ffsll((long long)vb) - 1;
-        const uint64_t klead = __shfl(key, lead);
-        const unsigned long long eq = __ballot(valid && key == klead);
-        bool go = valid;
-        const int ne = __popcll(eq);
-        if (ne > 1) {
-            const bool mine = (eq >> lane) & 1ull;
-            uint32_t s0, s1;
-            if (sg.keys) {
-                s0 = sg.side == 0 ? (uint32_t)ne : 0u;
-                s1 = sg.side == 1 ? (uint32_t)ne : 0u;
-            } else {
-                s0 = mine ? c0 : 0u;
-                s1 = mine ? c1 : 0u;
-                for (int o = 32; o; o >>= 1) {
-                    s0 += __shfl_xor(s0, o);
-                    s1 += __shfl_xor(s1, o);
+    const bool bare = sg.keys != nullptr;
+    const uint32_t b0 = sg.side == 0, b1 = sg.side == 1;
+    for (uint64_t e0 = 0; e0 < sg.n; e0 += (uint64_t)kWG * kAggBatch) {
+        if (__hip_atomic_load(&s_ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+        uint64_t key[kAggBatch];
+        uint32_t c0[kAggBatch], c1[kAggBatch];
+#pragma unroll
+        for (int u = 0; u < kAggBatch; ++u) {
+            const uint64_t e = e0 + (uint64_t)u * kWG + threadIdx.x;
+            key[u] = 0;
+            c0[u] = 0;
+            c1[u] = 0;
+            if (e < sg.n) {
+                if (bare) {
+                    key[u] = (uint64_t)__builtin_nontemporal_load(sg.keys + e);
+                    c0[u] = b0;
+                    c1[u] = b1;
+                } else {
+                    key[u] = sg.ent[e].key;
+                    c0[u] = sg.ent[e].c0;
+                    c1[u] = sg.ent[e].c1;
                 }
             }
-            if (mine) {
-                go = lane == lead;
-                c0 = s0;
-                c1 = s1;
-            }
         }
-        if (go) agg_insert(T, h, key, c0, c1, &s_ctl[0], &s_ctl[1]);
+#pragma unroll
+        for (int u = 0; u < kAggBatch; ++u)
+            agg_entry(T, bare, key[u], c0[u], c1[u], e0 + (uint64_t)u * kWG + threadIdx.x < sg.n, m, res, s_ctl,
+                      lane);
     }
 }
 
@@ -851,7 +1110,7 @@ __device__ void aggregate(AggLds& T, uint32_t nseg, SegAt&& seg_at, uint32_t* s_
             s_ctl[0] = 0;
             s_ctl[1] = 0;
         }
-        for (uint32_t i = threadIdx.x; i < kAggSlots; i += kWG) {
+        for (uint32_t i = threadIdx.x; i < T.slots; i += kWG) {
             T.key[i] = kEmptyKey;
             T.c0[i] = 0;
             T.c1[i] = 0;
@@ -875,7 +1134,7 @@ __device__ void aggregate(AggLds& T, uint32_t nseg, SegAt&& seg_at, uint32_t* s_
                 }
             }
         } else {
-            for (uint32_t i = threadIdx.x; i < kAggSlots; i += kWG) {
+            for (uint32_t i = threadIdx.x; i < T.slots; i += kWG) {
                 const unsigned long long k = T.key[i];
                 if (k == kEmptyKey) continue;
                 const uint32_t x = T.c0[i], y = T.c1[i];
@@ -938,6 +1197,7 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
             }
             __syncthreads();
             __threadfence();
+            agg_size(T, (uint64_t)kAggSlots);
             aggregate(
                 T, U.b,
                 [&](uint32_t c) {
@@ -974,6 +1234,7 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
             return sg;
         };
         const uint32_t nseg = (lo < nR ? 1u : 0u) + (hi > nR ? 1u : 0u);
+        agg_size(T, hi - lo);
         if (U.kind == AU_CHUNK) {
             aggregate(T, nseg, seg_at, s_ctl, stack, merge + (uint64_t)U.b * kChunkKeys, n0, n1, jn, acc);
             if (threadIdx.x == 0) {
@@ -1032,7 +1293,7 @@ __device__ __forceinline__ uint32_t pop_item(uint32_t* head, uint32_t first, uin
 }
 
 // selectivity scans (queue 0: items [0, n_scan_items))
-__global__ void __launch_bounds__(kWG) gace_scan_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 8))) gace_scan_kernel(BatchArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ uint32_t s_item;
     const PlanHdr H = *(const PlanHdr*)a.plan;
@@ -1083,8 +1344,17 @@ __global__ void __launch_bounds__(kWG) gace_join_kernel(BatchArgs a) {
                 jscatter_item(a, jd, it, lds);
                 signal_count(&acc.scatter_done);
                 break;
-            case IT_JAGG:
+            case IT_JSCATTER2:
                 wait_count(&acc.scatter_done, jd->n_items);
+                t1 = (uint64_t)wall_clock64();
+                jscatter2_item(a, jd, lds);
+                signal_count(&acc.s2_done);
+                break;
+            case IT_JAGG:
+                if (jd->log2P2)
+                    wait_count(&acc.s2_done, jd->n_s2);
+                else
+                    wait_count(&acc.scatter_done, jd->n_items);
                 t1 = (uint64_t)wall_clock64();
                 jagg_item(a, jd, it, lds);
                 break;

@@ -20,9 +20,12 @@ constexpr uint32_t kLutMaxEntries = 2048;              // LUT programs up to thi
 constexpr uint32_t kGroupTabBudget = 40u << 10;        // group tables staged in LDS up to this size
 constexpr uint64_t kEmptyKey = 0x8000000000000000ull;  // LDS table sentinel (INT64_MIN), counted out of band
 constexpr uint32_t kPartBitsMax = 13;                  // at most 8192 hash partitions per join
-constexpr uint32_t kAggSlots = 2048;                   // LDS key-table slots of one aggregation pass
-constexpr uint32_t kAggLimit = 1536;                   // distinct keys one pass may claim (load 0.75)
+constexpr uint32_t kAggSlots = 4096;                   // LDS key-table slots of one aggregation pass, at most
+constexpr uint32_t kAggMinSlots = 256;                 // ... and at least (a unit sizes its table to its keys)
 constexpr uint32_t kChunkKeys = 1u << 17;              // a partition with more keys is split into chunks + merge
+constexpr uint32_t kTileKeys = 4096;                   // keys staged in LDS per partitioning tile
+constexpr uint32_t kPass1BitsMax = 7;                  // first-pass fan-out at most 128 buckets
+constexpr uint32_t kUnit2Keys = 1u << 17;              // target keys per second-pass unit
 
 // column program kinds
 enum : uint32_t { CP_LUT32 = 1, CP_RANK32 = 2, CP_RANK64 = 3 };
@@ -96,10 +99,14 @@ struct JoinDesc {
     JoinSide side[2];        // 0 = R, 1 = S
     uint32_t acc;            // index of this join's JoinAcc
     uint32_t log2P;          // hash partitions: P = 2^log2P (top bits of the key hash)
-    uint32_t n_items;        // histogram / scatter items (R then S)
+    uint32_t n_items;        // histogram / first-pass scatter items (R then S)
     uint32_t n_off;          // offset items (64 partitions each)
     uint32_t n_agg;          // aggregation workers
-    uint32_t reserved;
+    uint32_t log2P2;         // second-pass fan-out bits (0: one pass writes the final partitions)
+    uint32_t group_items;    // second pass: items of one side per unit
+    uint32_t n_groups[2];    // second pass: item groups per side
+    uint32_t n_units2;       // second-pass units: (side, item group, first-pass bucket)
+    uint32_t n_s2;           // second-pass workers
     uint64_t rows_off;       // arena offset: per-item partition counts, then offsets, [n_items][P] u32
     uint64_t base_off;       // arena offset: [2][P + 1] u32 partition starts per side
     uint64_t stats_off;      // arena offset: per item {sampled keys, sentinel keys} u64
@@ -134,8 +141,10 @@ struct JoinAcc {
     unsigned long long nkeys[2];            // sampled keys per side other than the sentinel value
     unsigned long long status;              // 0 ok, 2 arena exhausted, 3 aggregation stack overflow
     unsigned long long merge_off;           // arena offset of the chunk tables (kChunkKeys entries per slot)
+    unsigned long long tmp_off;             // arena offset of the first-pass buffer (two-pass partitioning)
     uint32_t next_unit, n_units;
-    uint32_t hist_done, off_done, base_done, scatter_done, agg_done, reserved;
+    uint32_t hist_done, off_done, base_done, scatter_done, agg_done, s2_done;
+    uint32_t next_s2, reserved;
 };
 
 struct Arena {                              // bump allocator for partition buffers
@@ -143,7 +152,7 @@ struct Arena {                              // bump allocator for partition buff
 };
 
 // work item of the persistent batch kernel
-enum : uint32_t { IT_SCAN = 1, IT_JHIST = 2, IT_JOFF = 3, IT_JBASE = 4, IT_JSCATTER = 5, IT_JAGG = 6 };
+enum : uint32_t { IT_SCAN = 1, IT_JHIST = 2, IT_JOFF = 3, IT_JBASE = 4, IT_JSCATTER = 5, IT_JAGG = 6, IT_JSCATTER2 = 7 };
 struct Item {
     uint32_t kind;
     uint32_t idx;            // scan or join index

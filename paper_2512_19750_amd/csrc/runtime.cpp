@@ -12,6 +12,10 @@
 
 #include "plan.h"
 
+#ifndef GACE_SOURCE_HASH
+#define GACE_SOURCE_HASH "unversioned"
+#endif
+
 extern "C" {
 hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,
                             hipStream_t stream);
@@ -90,13 +94,19 @@ static uint32_t join_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.joi
 
 // init kernel, then the scan kernel on st and the join kernel on the side
 // stream concurrently (they touch disjoint state), joined back into st
-static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side) {
+static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, bool timed) {
     BatchArgsHost a = make_args(c);
     HIP_TRY(gace_launch_init(c->d_plan, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st), "init kernel");
     HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
     HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
+    if (timed) HIP_TRY(hipEventRecord(c->ev_j0, side), "event");
     HIP_TRY(gace_launch_join(&a, join_grid(c), side), "join kernel");
+    if (timed) {
+        HIP_TRY(hipEventRecord(c->ev_j1, side), "event");
+        HIP_TRY(hipEventRecord(c->ev_s0, st), "event");
+    }
     HIP_TRY(gace_launch_scan(&a, scan_grid(c), st), "scan kernel");
+    if (timed) HIP_TRY(hipEventRecord(c->ev_s1, st), "event");
     HIP_TRY(hipEventRecord(c->ev_join, side), "join event");
     HIP_TRY(hipStreamWaitEvent(st, c->ev_join, 0), "join wait");
     return GACE_OK;
@@ -113,7 +123,7 @@ static gace_status ensure_graph(gace_ctx* c) {
     if (c->graph_exec && std::memcmp(&c->graph_sched, &c->sched, sizeof(gace_schedule)) == 0) return GACE_OK;
     drop_graph(c);
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    gace_status st = launch_direct(c, c->cap_stream, c->cap_side);
+    gace_status st = launch_direct(c, c->cap_stream, c->cap_side, false);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (st != GACE_OK) {
@@ -154,8 +164,9 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
         if (gace_status s = ensure_graph(c)) return s;
         HIP_TRY(hipGraphLaunch(c->graph_exec, st), "graph launch");
     } else {
-        if (gace_status s = launch_direct(c, st, c->side_stream)) return s;
+        if (gace_status s = launch_direct(c, st, c->side_stream, true)) return s;
     }
+    c->last_timed = !use_graph;
     HIP_TRY(hipEventRecord(c->ev1, st), "event");
     uint8_t* hc = c->h_result;
     uint8_t* hh = hc + kCountsCap;
@@ -179,11 +190,16 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
 gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_kernel_ms = ms;
+    c->last_scan_ms = c->last_join_ms = 0.0;
+    if (c->last_timed) {
+        if (hipEventElapsedTime(&ms, c->ev_s0, c->ev_s1) == hipSuccess) c->last_scan_ms = ms;
+        if (hipEventElapsedTime(&ms, c->ev_j0, c->ev_j1) == hipSuccess) c->last_join_ms = ms;
+    }
     const uint8_t* hc = c->h_result;
     const unsigned long long* counts = (const unsigned long long*)hc;
     const unsigned long long* hist = (const unsigned long long*)(hc + kCountsCap);
     const JoinAcc* accs = (const JoinAcc*)(hc + kCountsCap + kHistCap);
-    uint64_t alg = 0, rp = 0;
+    uint64_t alg = 0, rp = 0, jalg = 0;
     for (const ScanDesc& S : cb.scans) {
         uint64_t kept_rows = 0;
         for (uint32_t k = 1; k <= S.n_req; ++k) kept_rows += hist[S.hist_off + 2 * k];
@@ -222,12 +238,14 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
             r.join->ndv_S = A.ndv[1];
             r.join->n_R = A.n[0];
             r.join->n_S = A.n[1];
-            alg += 8ull * (A.n[0] + A.n[1]);
+            jalg += 8ull * (A.n[0] + A.n[1]) + 16ull * (A.ndv[0] + A.ndv[1]);
         }
         if (per_req) per_req[jo.req] = s;
         if (s != GACE_OK && worst == GACE_OK) worst = s;
     }
-    c->last_alg_bytes = alg;
+    c->last_scan_bytes = alg;
+    c->last_join_bytes = jalg;
+    c->last_alg_bytes = alg + jalg;
     c->last_rows_preds = rp;
     return worst;
 }
@@ -341,6 +359,8 @@ gace_status gace_create(int hip_device, uint64_t workspace_bytes, gace_ctx** out
     if (hipHostMalloc((void**)&c->h_stage, kPlanCap + kItemsCap, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->h_result, kCountsCap + kHistCap + kAccsCap, hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreate(&c->ev_s0) != hipSuccess || hipEventCreate(&c->ev_s1) != hipSuccess ||
+        hipEventCreate(&c->ev_j0) != hipSuccess || hipEventCreate(&c->ev_j1) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
@@ -379,6 +399,8 @@ gace_status gace_destroy(gace_ctx* c) {
     if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
     if (c->cap_side) (void)hipStreamDestroy(c->cap_side);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (hipEvent_t e : {c->ev_s0, c->ev_s1, c->ev_j0, c->ev_j1})
+        if (e) (void)hipEventDestroy(e);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_result) (void)hipHostFree(c->h_result);
     if (c->ws) (void)hipFree(c->ws);
@@ -436,7 +458,7 @@ gace_status gace_batch_run(gace_ctx* ctx, const gace_request* reqs, uint32_t n, 
     }
     auto it = ctx->tuned.find(shape_bucket(reqs, n));
     if (it != ctx->tuned.end()) ctx->sched = it->second;
-    return run_requests(ctx, reqs, n, per_req, (hipStream_t)stream, true);
+    return run_requests(ctx, reqs, n, per_req, (hipStream_t)stream, ctx->use_graph);
 }
 
 gace_status gace_get_schedule(gace_ctx* ctx, gace_schedule* out) {
@@ -487,6 +509,29 @@ gace_status gace_last_batch_stats(gace_ctx* ctx, double* kernel_ms, uint64_t* al
     if (kernel_ms) *kernel_ms = ctx->last_kernel_ms;
     if (alg_bytes) *alg_bytes = ctx->last_alg_bytes;
     if (rows_preds) *rows_preds = ctx->last_rows_preds;
+    return GACE_OK;
+}
+
+gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out) {
+    if (!ctx || !out) {
+        set_error("NULL argument");
+        return GACE_EINVAL;
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->timed = ctx->last_timed ? 1u : 0u;
+    out->scan_ms = ctx->last_scan_ms;
+    out->join_ms = ctx->last_join_ms;
+    out->scan_alg_bytes = ctx->last_scan_bytes;
+    out->join_alg_bytes = ctx->last_join_bytes;
+    return GACE_OK;
+}
+
+gace_status gace_set_graph(gace_ctx* ctx, int enable) {
+    if (!ctx) {
+        set_error("NULL context");
+        return GACE_EINVAL;
+    }
+    ctx->use_graph = enable != 0;
     return GACE_OK;
 }
 
@@ -556,7 +601,9 @@ gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, c
     }
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "device properties");
-    const std::string prefix = std::string(prop.gcnArchName) + ":" + std::to_string(ctx->n_cu) + ":";
+    // schedules are only valid for the kernels they were timed on
+    const std::string prefix = std::string(prop.gcnArchName) + ":" + std::to_string(ctx->n_cu) + ":" +
+                               GACE_SOURCE_HASH + ":";
     const std::string bucket = shape_bucket(reqs, n);
     load_cache(ctx, cache_path, prefix);
     auto hit = ctx->tuned.find(bucket);
@@ -585,7 +632,7 @@ gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, c
     const uint32_t rows[] = {16384, 32768, 65536, 131072, 262144};
     const uint32_t modes[] = {0, 1, 2};
     const uint32_t parts[] = {512, 1024, 2048};
-    const uint32_t jwgs[] = {2, 3, 4};
+    const uint32_t jwgs[] = {1, 2, 3, 4};
     for (int pass = 0; pass < 2; ++pass) {
         for (uint32_t v : wgs) {
             gace_schedule s = best; s.wgs_per_cu = v; double ms;

@@ -47,6 +47,9 @@ struct gace_ctx {
     uint8_t* h_stage = nullptr;     // plan + items upload
     uint8_t* h_result = nullptr;    // counts + hist + accs download
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr, ev_fork = nullptr, ev_join = nullptr;
+    // per-kernel timing of direct launches: scan kernel on the call's stream, join kernel on the side stream
+    hipEvent_t ev_s0 = nullptr, ev_s1 = nullptr, ev_j0 = nullptr, ev_j1 = nullptr;
+    bool use_graph = true;                        // batched path: replay the captured graph
     hipStream_t side_stream = nullptr;   // join kernel runs here, concurrently with the scan kernel
     gace_schedule sched{};
     // graph of (init kernel, batch kernel) for the current schedule
@@ -57,6 +60,9 @@ struct gace_ctx {
     // stats of the last batch
     double last_kernel_ms = 0.0;
     uint64_t last_alg_bytes = 0, last_rows_preds = 0;
+    bool last_timed = false;                      // last batch ran by direct launch with per-kernel events
+    double last_scan_ms = 0.0, last_join_ms = 0.0;
+    uint64_t last_scan_bytes = 0, last_join_bytes = 0;
     std::map<std::string, gace_schedule> tuned;   // shape bucket -> schedule
     bool trace = false;                           // record per-item device timestamps
     std::vector<TraceRec> last_trace;

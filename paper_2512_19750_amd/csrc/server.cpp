@@ -45,7 +45,14 @@ struct ServeSlot {
 struct TicketState {
     bool done = false;
     gace_status st = GACE_OK;
+    uint64_t submit_ns = 0, done_ns = 0;   // CLOCK_MONOTONIC
 };
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
 
 // device bytes a join needs: its partitioned key buffer (8 bytes per sampled
 // key, bounded by the expected kept blocks plus 12 standard deviations) and
@@ -62,7 +69,10 @@ uint64_t join_bytes(const gace_request& r) {
         uint64_t k = kept >= (double)nb ? nb : (uint64_t)kept;
         U += std::min<uint64_t>(s[i]->n, k * B);
     }
-    return 8 * U + (U / 2048) * 4 * 8192 / 64 + (1ull << 20);
+    // partitioned keys and the first-pass buffer (8 + 8 bytes per key), the
+    // per-item partition counts (at most U / 8 bytes) and chunk tables of
+    // partitions split by hot keys (about 8 bytes per key for Zipf-skewed keys)
+    return 24 * U + U / 8 + (1ull << 20);
 }
 
 }  // namespace
@@ -99,11 +109,13 @@ bool gace_server::try_complete(ServeSlot& s, std::unique_lock<std::mutex>& lk) {
         for (auto& p : s.per) p = GACE_EDEVICE;
     }
     lk.lock();
+    const uint64_t t_done = now_ns();
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         OwnedRequest& o = *s.reqs[i];
         TicketState& t = tickets[o.ticket];
         t.done = true;
         t.st = s.per[i];
+        t.done_ns = t_done;
     }
     stats.completed += s.reqs.size();
     stats.inflight -= s.reqs.size();
@@ -145,10 +157,12 @@ bool gace_server::try_launch(ServeSlot& s, std::unique_lock<std::mutex>& lk) {
     gace_status st = gace::launch_compiled(s.ctx, s.cb, s.stream, true);
     lk.lock();
     if (st != GACE_OK) {
+        const uint64_t t_done = now_ns();
         for (auto& o : s.reqs) {
             TicketState& t = tickets[o->ticket];
             t.done = true;
             t.st = st;
+            t.done_ns = t_done;
         }
         stats.completed += s.reqs.size();
         stats.inflight -= s.reqs.size();
@@ -262,7 +276,9 @@ gace_status gace_server_submit(gace_server* srv, const gace_request* req, uint64
     }
     o->ticket = srv->next_ticket++;
     *ticket = o->ticket;
-    srv->tickets[o->ticket] = TicketState();
+    TicketState ts;
+    ts.submit_ns = now_ns();
+    srv->tickets[o->ticket] = ts;
     srv->queue.push_back(std::move(o));
     srv->stats.submitted += 1;
     srv->stats.queued = srv->queue.size();
@@ -271,6 +287,11 @@ gace_status gace_server_submit(gace_server* srv, const gace_request* req, uint64
 }
 
 gace_status gace_server_wait(gace_server* srv, uint64_t ticket, int64_t timeout_ns, gace_status* req_status) {
+    return gace_server_wait_times(srv, ticket, timeout_ns, req_status, nullptr, nullptr);
+}
+
+gace_status gace_server_wait_times(gace_server* srv, uint64_t ticket, int64_t timeout_ns, gace_status* req_status,
+                                   uint64_t* submit_ns, uint64_t* done_ns) {
     if (!srv) {
         set_error("NULL server");
         return GACE_EINVAL;
@@ -288,7 +309,10 @@ gace_status gace_server_wait(gace_server* srv, uint64_t ticket, int64_t timeout_
         set_error("request still running");
         return GACE_ETIMEOUT;
     }
-    if (req_status) *req_status = srv->tickets[ticket].st;
+    const TicketState& t = srv->tickets[ticket];
+    if (req_status) *req_status = t.st;
+    if (submit_ns) *submit_ns = t.submit_ns;
+    if (done_ns) *done_ns = t.done_ns;
     srv->tickets.erase(ticket);
     return GACE_OK;
 }

@@ -212,6 +212,30 @@ def test_join_cache_settings_agree(g, torch_dev, cache):
     assert got == oracle.join_request(w, 0)
 
 
+@pytest.mark.parametrize("B,rate,part", [(1, 0.5, 1024), (16, 0.7, 256), (512, 1.0, 128), (4096, 1.0, 256),
+                                          (1 << 16, 0.6, 1024)])
+def test_join_two_pass_vs_oracle(g, torch_dev, B, rate, part):
+    """Wide fan-outs (two partitioning passes) over kept-block streams of
+    several block sizes, skewed keys and the sentinel value."""
+    import torch
+    rng = np.random.default_rng(B * 7 + part)
+    nr, ns = 1_500_000, 600_000
+    r = (rng.zipf(1.2, nr) % 300_000).astype(np.int64) * 7919 - 123_456
+    s = rng.integers(-50_000, 400_000, size=ns, dtype=np.int64) * 7919 - 123_456
+    r[rng.random(nr) < 0.001] = INT64_MIN
+    s[rng.random(ns) < 0.001] = INT64_MIN
+    _say("two-pass join", B, rate, part)
+    kr = torch.from_numpy(r).to(torch_dev)
+    ks = torch.from_numpy(s).to(torch_dev)
+    c = g.gace_create(0, 2 << 30)
+    try:
+        g.gace_set_schedule(c, join_part_keys=part)
+        got = _join(g, c, kr, ks, 8, 9, 23, 29, rate, rate, B, B)
+    finally:
+        g.gace_destroy(c)
+    assert got == oracle.join_freq(r, 8, 23, rate, B, s, 9, 29, rate, B)
+
+
 @pytest.mark.parametrize("rate", [1.0, 0.05])
 def test_config3_reduced(g, ctx, torch_dev, rate):
     w = datagen.config3(rate=rate, n_r=20_000_000, n_s=5_000_000, domain=1_000_000)
@@ -309,6 +333,18 @@ def test_batch_repeatable_and_schedules_agree(g, torch_dev):
                 g.gace_batch_run(c, reqs)
                 results.append([q.result() if isinstance(q, g.JoinRequest) else
                                 (q.result()[0].tolist(), q.result()[1:]) for q in reqs])
+        # direct launches with per-kernel timing events give the same results
+        g.gace_set_graph(c, False)
+        reqs = _requests(g, w, tabs, keys)
+        g.gace_batch_run(c, reqs)
+        results.append([q.result() if isinstance(q, g.JoinRequest) else
+                        (q.result()[0].tolist(), q.result()[1:]) for q in reqs])
+        ks = g.gace_last_kernel_stats(c)
+        assert ks["timed"] and ks["scan_ms"] > 0 and ks["join_ms"] > 0
+        assert ks["scan_alg_bytes"] > 0 and ks["join_alg_bytes"] > 0
+        g.gace_set_graph(c, True)
+        g.gace_batch_run(c, _requests(g, w, tabs, keys))
+        assert not g.gace_last_kernel_stats(c)["timed"]
         for r in results[1:]:
             assert r == results[0]
     finally:

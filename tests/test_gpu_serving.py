@@ -113,7 +113,8 @@ def test_server_rejects_invalid_and_oversized(env):
         assert e.value.status == g.GACE_ENOMEM
         ok = _req(g, w, tabs, keys, "sel", 0)
         t = g.gace_server_submit(srv, ok)
-        assert g.gace_server_wait(srv, t, 60_000_000_000) == 0
+        st, t_sub, t_done = g.gace_server_wait_times(srv, t, 60_000_000_000)
+        assert st == 0 and 0 < t_sub <= t_done
         st = g.gace_server_stats_get(srv)
         assert st["rejected"] == 2 and st["completed"] == 1
         del big
@@ -131,7 +132,38 @@ def test_tracing_records_every_item(env):
         tr, tpu = g.gace_get_trace(ctx)
         assert len(tr) > 0 and tpu > 0
         assert np.all(tr["t_end"] >= tr["t_ready"]) and np.all(tr["t_ready"] >= tr["t_begin"])
-        assert set(np.unique(tr["kind"]).tolist()) <= {1, 2, 3, 4, 5, 6}
+        assert set(np.unique(tr["kind"]).tolist()) <= {1, 2, 3, 4, 5, 6, 7}
         assert np.all(tr["xcc"] < 16)
     finally:
         g.gace_destroy(ctx)
+
+
+def test_open_loop_stream_equals_plain(env):
+    """The benchmark's open-loop Poisson driver: every served result equals the
+    request's plain-path result, and latencies are measured for the counted
+    arrivals."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    g, w, tabs, keys = env
+    reqs = [_req(g, w, tabs, keys, k, i) for k, i in w.order]
+    kinds = [k for k, _ in w.order]
+    ctx = g.gace_create(0, 2 << 30)
+    expect = []
+    try:
+        for q in reqs:
+            if isinstance(q, g.JoinRequest):
+                r = g.gace_join_freq(ctx, q.R, q.S)
+                expect.append((r["join_card"], r["ndv_R"], r["ndv_S"], r["n_R"], r["n_S"]))
+            else:
+                c, n, b = g.gace_probe_selectivity(ctx, q.table, q.preds, q.seed, q.rate, q.block_rows)
+                expect.append((tuple(int(x) for x in c), n, b))
+    finally:
+        g.gace_destroy(ctx)
+    arr, keep = g.make_requests(reqs)
+    r = bench.serve_point(g, arr, expect, kinds, 400.0,
+                          dict(max_inflight=2, max_batch=16, queue_capacity=512, workspace_bytes=3 << 30),
+                          seed=5, duration_s=2.0, warm_s=0.2, ring=1024)
+    assert r["mismatches"] == 0 and r["rejected_busy"] == 0
+    assert r["counted"] > 0 and r["p99_ms"] >= r["p50_ms"] > 0
