@@ -264,7 +264,7 @@ typedef struct {
     uint32_t wg;      /* workgroup id */
     uint32_t xcc;     /* XCD (accelerator complex die) the workgroup ran on */
     uint64_t t_begin, t_ready, t_end;
-    uint64_t reserved;
+    uint64_t work;    /* join aggregation: units taken << 32 | LDS table passes; else 0 */
 } gace_trace_rec;
 
 gace_status gace_set_trace(gace_ctx* ctx, int enable);

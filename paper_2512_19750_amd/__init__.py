@@ -87,7 +87,7 @@ class gace_schedule(ctypes.Structure):
 class gace_trace_rec(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_uint32), ("index", ctypes.c_uint32), ("wg", ctypes.c_uint32),
                 ("xcc", ctypes.c_uint32), ("t_begin", ctypes.c_uint64), ("t_ready", ctypes.c_uint64),
-                ("t_end", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
+                ("t_end", ctypes.c_uint64), ("work", ctypes.c_uint64)]
 
 
 class gace_kernel_stats(ctypes.Structure):
@@ -439,7 +439,7 @@ def gace_get_trace(ctx: int):
     recs = (gace_trace_rec * max(n.value, 1))()
     _check(lib().gace_get_trace(ctx, recs, n.value, ctypes.byref(n), ctypes.byref(tpu)))
     dt = np.dtype([("kind", "<u4"), ("index", "<u4"), ("wg", "<u4"), ("xcc", "<u4"), ("t_begin", "<u8"),
-                   ("t_ready", "<u8"), ("t_end", "<u8"), ("reserved", "<u8")])
+                   ("t_ready", "<u8"), ("t_end", "<u8"), ("work", "<u8")])
     arr = np.frombuffer(bytes(recs), dtype=dt, count=n.value).copy()
     return arr, tpu.value
 

@@ -31,16 +31,21 @@ constexpr uint32_t kLdsHist = kScanLdsHist * 2 * 8;
 constexpr uint32_t kLdsThr = kScanLdsHist * 8 + 640;                             // thresholds + bit prefix sums
 constexpr uint32_t kLdsBytes = kLdsMisc + kLdsCnt + kLdsHist + kLdsThr + kGroupTabBudget;   // scan kernel
 constexpr int kPer = kTileKeys / kWG;                                              // staged keys per thread
-constexpr uint32_t kTileLdsBytes = 3 * 132 * 4 + kTileKeys * 8 + kTileKeys;          // cursors, counts, starts, tile
+constexpr uint32_t kTileLdsBytes = 3 * 132 * 4 + kTileKeys * 12;                     // cursors, counts, starts, tile
 constexpr uint32_t kAggLdsBytes = kAggSlots * 16 + 512;                             // key table + split stack
+constexpr uint32_t kBaseLdsBytes = 2 * ((1u << kPartBitsMax) + 1) * 4;                 // staged partition starts
+constexpr uint32_t lds_max(uint32_t x, uint32_t y) { return x > y ? x : y; }
 constexpr uint32_t kJoinLdsBytes =
-    kLdsMisc + (kTileLdsBytes > kAggLdsBytes ? (kTileLdsBytes > 8192 * 4 ? kTileLdsBytes : 8192 * 4)
-                                             : (kAggLdsBytes > 8192 * 4 ? kAggLdsBytes : 8192 * 4));
+    kLdsMisc + lds_max(lds_max(kTileLdsBytes, kAggLdsBytes), lds_max(kBaseLdsBytes, (1u << kPartBitsMax) * 4));
 
 // explicit address spaces: pointers read from the plan are generic to the
 // compiler; global loads through them must not become flat loads, which would
 // make every LDS wait also wait for the loads in flight
 #define GACE_GLOBAL __attribute__((address_space(1)))
+// the plan is written before a launch and only read by the kernels: read
+// through the constant address space, uniform plan fields become scalar loads,
+// which do not wait behind the vector loads a wave has in flight
+#define GACE_CONST __attribute__((address_space(4)))
 #define GACE_LDS __attribute__((address_space(3)))
 
 struct BatchArgs {
@@ -61,7 +66,7 @@ struct BatchArgs {
 __device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u; }
 
 __device__ __forceinline__ void trace_item(const BatchArgs& a, const PlanHdr& H, uint32_t idx, const Item& it,
-                                           uint64_t t0, uint64_t t1) {
+                                           uint64_t t0, uint64_t t1, uint64_t work = 0) {
     if (!H.trace || threadIdx.x) return;
     TraceRec r;
     r.kind = it.kind;
@@ -71,7 +76,7 @@ __device__ __forceinline__ void trace_item(const BatchArgs& a, const PlanHdr& H,
     r.t_begin = t0;
     r.t_ready = t1;
     r.t_end = (uint64_t)wall_clock64();
-    r.reserved = 0;
+    r.work = work;
     a.trace[idx] = r;
 }
 
@@ -102,39 +107,36 @@ __device__ __forceinline__ uint32_t key32(uint32_t v, uint32_t xf) {
     return (v & 0x80000000u) ? ~v : (v | 0x80000000u);
 }
 
-template <typename B>
-__device__ __forceinline__ uint32_t rank32(const B* bnd, uint32_t nb, uint32_t step, uint32_t k) {
-    uint32_t pos = 0;
-    for (; step; step >>= 1)
-        if (pos + step <= nb && bnd[pos + step - 1] <= k) pos += step;
-    return pos;
-}
-
-template <typename B>
-__device__ __forceinline__ uint32_t rank64(const B* bnd, uint32_t nb, uint32_t step, uint64_t k) {
-    uint32_t pos = 0;
-    for (; step; step >>= 1)
-        if (pos + step <= nb && bnd[pos + step - 1] <= k) pos += step;
-    return pos;
-}
-
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 // value -> elementary-interval index of one column program; AS is the
 // address space of the group's tables (LDS when staged, else global)
-template <int AS>
-__device__ __forceinline__ uint32_t interval32(const ColProg& P, const uint8_t* tab, uint32_t v) {
-    typedef __attribute__((address_space(AS))) const uint32_t TB;
-    const uint32_t k = key32(v, P.xform);
-    if (P.kind == CP_LUT32) return min(max(k, P.lo), P.hi) - P.lo;
-    return rank32((TB*)(tab + P.bnd_off), P.nb, P.step, k);
+// field-wise copies of plan descriptors read through the constant address space
+__device__ __forceinline__ ColProg cprog(const GACE_CONST ColProg* p) {
+    ColProg P;
+    P.data = p->data;
+    P.kind = p->kind;
+    P.xform = p->xform;
+    P.lo = p->lo;
+    P.hi = p->hi;
+    P.nb = p->nb;
+    P.step = p->step;
+    P.mask_off = p->mask_off;
+    P.bnd_off = p->bnd_off;
+    return P;
 }
 
-template <int AS>
-__device__ __forceinline__ uint32_t interval64(const ColProg& P, const uint8_t* tab, uint64_t v) {
-    typedef __attribute__((address_space(AS))) const uint64_t TB;
-    return rank64((TB*)(tab + P.bnd_off), P.nb, P.step, v ^ 0x8000000000000000ull);
+__device__ __forceinline__ GroupDesc cgroup(const GACE_CONST GroupDesc* p) {
+    GroupDesc G;
+    G.base_mask = p->base_mask;
+    G.col_begin = p->col_begin;
+    G.col_end = p->col_end;
+    G.slot_index = p->slot_index;
+    G.tab_off = p->tab_off;
+    G.tab_bytes = p->tab_bytes;
+    G.n_used = p->n_used;
+    return G;
 }
 
 // ------------------------------------------------------------------ counting
@@ -208,13 +210,44 @@ __device__ __forceinline__ void load32(const ColProg& P, uint64_t q0, uint64_t r
     }
 }
 
+// binary searches of n keys advanced together: each step issues n
+// independent boundary reads instead of n dependent chains
+template <int N, typename B, typename K>
+__device__ __forceinline__ void rank_many(const B* bnd, uint32_t nb, uint32_t step, const K (&k)[N],
+                                          uint32_t (&pos)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) pos[i] = 0;
+    for (; step; step >>= 1) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (pos[i] + step <= nb && bnd[pos[i] + step - 1] <= k[i]) pos[i] += step;
+    }
+}
+
+// the column's kind and key transform are dispatched once for all rows
 template <int AS>
 __device__ __forceinline__ void lookup32(const ColProg& P, const uint8_t* tab, const uint32_t (&v)[kRows],
                                          uint64_t (&m)[kRows]) {
     typedef __attribute__((address_space(AS))) const uint64_t TM;
+    typedef __attribute__((address_space(AS))) const uint32_t TB;
     TM* masks = (TM*)(tab + P.mask_off);
+    uint32_t k[kRows];
+    if (P.xform == XF_I32) {
 #pragma unroll
-    for (int i = 0; i < kRows; ++i) m[i] &= masks[interval32<AS>(P, tab, v[i])];
+        for (int i = 0; i < kRows; ++i) k[i] = v[i] ^ 0x80000000u;
+    } else {
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) k[i] = key32(v[i], XF_F32);
+    }
+    if (P.kind == CP_LUT32) {
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) m[i] &= masks[min(max(k[i], P.lo), P.hi) - P.lo];
+    } else {
+        uint32_t pos[kRows];
+        rank_many<kRows>((TB*)(tab + P.bnd_off), P.nb, P.step, k, pos);
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) m[i] &= masks[pos[i]];
+    }
 }
 
 template <int AS>
@@ -236,8 +269,14 @@ __device__ __forceinline__ void lookup64(const ColProg& P, const uint8_t* tab, u
 #pragma unroll
             for (int t = 0; t < 4; ++t) w[t] = t < nv ? p[t] : 0ull;
         }
+        uint64_t kk[4];
+        uint32_t pos[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) m[4 * j + t] &= masks[interval64<AS>(P, tab, w[t])];
+        for (int t = 0; t < 4; ++t) kk[t] = w[t] ^ 0x8000000000000000ull;
+        typedef __attribute__((address_space(AS))) const uint64_t TB;
+        rank_many<4>((TB*)(tab + P.bnd_off), P.nb, P.step, kk, pos);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) m[4 * j + t] &= masks[pos[t]];
     }
 }
 
@@ -275,61 +314,147 @@ __device__ __forceinline__ bool tile_next(TileIt& t, unsigned long long& rest, u
 
 // all rows of the blocks in `blocks` (bit j = block cb + j) for group g: a
 // block's active predicates are the group's bits among the first s_act[j]
-// predicate bits of the scan.  The 32-bit column loads of the next column --
-// or of the next tile's first column after the last one -- are issued before
-// the current column's lookups, so each lane keeps 4-8 loads of 16 B in
-// flight across all the blocks.  tab points at the group's masks/boundaries
-// in address space AS (LDS when staged, else global).
+// predicate bits of the scan.  tab points at the group's masks/boundaries in
+// address space AS (LDS when staged, else global).
+//
+// Full tiles (4096 rows inside one block) form a stream of units (tile,
+// 32-bit column) with two register buffers that alternate, so a unit's four
+// 16-byte loads per lane are in flight while the previous unit is looked up;
+// their loads have one form and no bounds, so nothing makes the wave wait for
+// them early.  Short tiles (blocks of fewer than 4096 rows, a table's last
+// block) take a second, unpipelined pass with per-row bounds.  64-bit columns
+// are loaded and looked up at the end of each tile.
+struct ScanUnit {
+    TileIt t;
+    unsigned long long rest;    // blocks after t's block
+    uint32_t c;                 // column
+    bool valid;
+};
+
+__device__ __forceinline__ bool tile_full(const TileIt& t) { return t.end - t.start >= (uint64_t)kWG * kRows; }
+
+// next tile of the requested kind (full or short) after t, or of blocks in rest
+__device__ __forceinline__ bool tile_next_kind(TileIt& t, unsigned long long& rest, uint64_t cb, uint64_t B,
+                                               uint64_t n, bool full, bool first) {
+    bool ok = first ? tile_first(t, rest, cb, B, n) : tile_next(t, rest, cb, B, n);
+    while (ok && tile_full(t) != full) ok = tile_next(t, rest, cb, B, n);
+    return ok;
+}
+
+__device__ __forceinline__ void load32_full(const ColProg& P, uint64_t q0, uint32_t (&v)[kRows]) {
+#pragma unroll
+    for (int j = 0; j < kQuads; ++j) {
+        const GACE_GLOBAL u32x4* p = (const GACE_GLOBAL u32x4*)((const GACE_GLOBAL uint32_t*)P.data + q0 + 256ull * j);
+        const u32x4 x = __builtin_nontemporal_load(p);
+        v[4 * j + 0] = x.x;
+        v[4 * j + 1] = x.y;
+        v[4 * j + 2] = x.z;
+        v[4 * j + 3] = x.w;
+    }
+}
+
 template <int AS>
-__device__ __forceinline__ uint32_t scan_blocks(const ColProg* cols, uint32_t c_begin, uint32_t c_end,
+__device__ __forceinline__ uint32_t scan_blocks(const GACE_CONST ColProg* cols, uint32_t c_begin, uint32_t c_end,
                                                 const uint8_t* tab, unsigned long long blocks, uint64_t cb,
                                                 uint64_t B, uint64_t n, uint64_t base_mask, const uint32_t* s_act,
                                                 uint32_t g, int lane, int wave, uint32_t mode) {
     uint32_t cnt = 0;
-    uint32_t first32 = c_begin;
-    while (first32 < c_end && cols[first32].kind == CP_RANK64) ++first32;
+    auto next32 = [&](uint32_t c) __attribute__((always_inline)) {
+        while (c < c_end && cols[c].kind == CP_RANK64) ++c;
+        return c;
+    };
+    const uint32_t first32 = next32(c_begin);
     bool any64 = false;
     for (uint32_t c = c_begin; c < c_end; ++c) any64 |= cols[c].kind == CP_RANK64;
-    unsigned long long rest = blocks;
-    TileIt t;
-    if (!tile_first(t, rest, cb, B, n)) return 0;
     const uint64_t lane_off = (uint64_t)wave * 256 * kQuads + 4ull * (uint64_t)lane;
-    uint32_t cur[kRows], nxt[kRows];
-    if (first32 < c_end) load32(cols[first32], t.start + lane_off, t.end, cur);
-    for (;;) {
+    uint64_t m[kRows];
+    // end of a tile: 64-bit columns, then count the tile's rows
+    auto finish_tile = [&](const TileIt& t, uint64_t active) __attribute__((always_inline)) {
         const uint64_t q0 = t.start + lane_off, r1 = t.end;
-        TileIt tn = t;
-        unsigned long long rest_n = rest;
-        const bool has_next = tile_next(tn, rest_n, cb, B, n);
-        const uint64_t active = base_mask & group_prefix(s_act[t.j], g);
-        uint64_t m[kRows];
-#pragma unroll
-        for (int i = 0; i < kRows; ++i) m[i] = active;
-        uint32_t c = first32;
-        while (c < c_end) {
-            uint32_t cn = c + 1;
-            while (cn < c_end && cols[cn].kind == CP_RANK64) ++cn;
-            if (cn < c_end) load32(cols[cn], q0, r1, nxt);
-            else if (has_next) load32(cols[first32], tn.start + lane_off, tn.end, nxt);
-            lookup32<AS>(cols[c], tab, cur, m);
-            if (cn < c_end || has_next) {
-#pragma unroll
-                for (int i = 0; i < kRows; ++i) cur[i] = nxt[i];
-            }
-            c = cn;
-        }
         if (any64)
             for (uint32_t c64 = c_begin; c64 < c_end; ++c64)
-                if (cols[c64].kind == CP_RANK64) lookup64<AS>(cols[c64], tab, q0, r1, m);
+                if (cols[c64].kind == CP_RANK64) {
+                    const ColProg P64 = cprog(cols + c64);
+                    lookup64<AS>(P64, tab, q0, r1, m);
+                }
 #pragma unroll
         for (int j = 0; j < kQuads; ++j) {
             const uint64_t rq = q0 + 256ull * j;
 #pragma unroll
             for (int u = 0; u < 4; ++u) count_rows(rq + u < r1 ? m[4 * j + u] : 0ull, active, cnt, lane, mode);
         }
-        if (!has_next) break;
-        t = tn;
-        rest = rest_n;
+    };
+
+    // ---- full tiles, pipelined over (tile, column) units
+    if (first32 < c_end) {
+        ScanUnit u0;
+        u0.rest = blocks;
+        u0.valid = tile_next_kind(u0.t, u0.rest, cb, B, n, true, true);
+        u0.c = first32;
+        auto advance = [&](ScanUnit u) __attribute__((always_inline)) {
+            u.c = next32(u.c + 1);
+            if (u.c >= c_end) {
+                u.valid = tile_next_kind(u.t, u.rest, cb, B, n, true, false);
+                u.c = first32;
+            }
+            return u;
+        };
+        // a tile's first column starts its masks, its last one finishes it
+        auto consume = [&](const ScanUnit& u, const uint32_t (&v)[kRows]) __attribute__((always_inline)) {
+            const uint64_t active = base_mask & group_prefix(s_act[u.t.j], g);
+            if (u.c == first32) {
+#pragma unroll
+                for (int i = 0; i < kRows; ++i) m[i] = active;
+            }
+            const ColProg Pc = cprog(cols + u.c);
+            lookup32<AS>(Pc, tab, v, m);
+            if (next32(u.c + 1) >= c_end) finish_tile(u.t, active);
+        };
+        if (u0.valid) {
+            uint32_t va[kRows], vb[kRows];
+            {
+                const ColProg P = cprog(cols + u0.c);
+                load32_full(P, u0.t.start + lane_off, va);
+            }
+            for (;;) {
+                const ScanUnit u1 = advance(u0);
+                if (u1.valid) {
+                    const ColProg P = cprog(cols + u1.c);
+                    load32_full(P, u1.t.start + lane_off, vb);
+                }
+                consume(u0, va);
+                if (!u1.valid) break;
+                const ScanUnit u2 = advance(u1);
+                if (u2.valid) {
+                    const ColProg P = cprog(cols + u2.c);
+                    load32_full(P, u2.t.start + lane_off, va);
+                }
+                consume(u1, vb);
+                if (!u2.valid) break;
+                u0 = u2;
+            }
+        }
+    }
+
+    // ---- short tiles (and groups with only 64-bit columns): one at a time
+    {
+        const bool only64 = first32 >= c_end;
+        TileIt t;
+        unsigned long long rest = blocks;
+        bool ok = only64 ? tile_first(t, rest, cb, B, n) : tile_next_kind(t, rest, cb, B, n, false, true);
+        while (ok) {
+            const uint64_t active = base_mask & group_prefix(s_act[t.j], g);
+#pragma unroll
+            for (int i = 0; i < kRows; ++i) m[i] = active;
+            for (uint32_t c = first32; c < c_end; c = next32(c + 1)) {
+                const ColProg P = cprog(cols + c);
+                uint32_t v[kRows];
+                load32(P, t.start + lane_off, t.end, v);
+                lookup32<AS>(P, tab, v, m);
+            }
+            finish_tile(t, active);
+            ok = only64 ? tile_next(t, rest, cb, B, n) : tile_next_kind(t, rest, cb, B, n, false, false);
+        }
     }
     return cnt;
 }
@@ -352,10 +477,10 @@ __device__ __forceinline__ void decide_blocks(uint64_t cb, uint64_t b_end, uint6
 }
 
 // ------------------------------------------------------------------ scan item
-__device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, uint8_t* lds) {
+__device__ __forceinline__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, uint8_t* lds) {
     const ScanDesc S = ((const ScanDesc*)(a.plan + H.scans_off))[it.idx];
-    const GroupDesc* groups = (const GroupDesc*)(a.plan + H.groups_off) + S.group_begin;
-    const ColProg* cols = (const ColProg*)(a.plan + H.cols_off);
+    const GACE_CONST GroupDesc* groups = (const GACE_CONST GroupDesc*)(a.plan + H.groups_off) + S.group_begin;
+    const GACE_CONST ColProg* cols = (const GACE_CONST ColProg*)(a.plan + H.cols_off);
     const uint32_t* slots = (const uint32_t*)(a.plan + H.slots_off);
     const uint64_t* rthr = (const uint64_t*)(a.plan + H.reqthr_off) + S.req_begin;
     const uint32_t* rcum = (const uint32_t*)(a.plan + H.reqcum_off) + S.req_begin;
@@ -416,7 +541,7 @@ __device__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, 
             for (uint32_t g = 0;; ++g) {
                 const unsigned long long blocks_g = __ballot(((keep >> lane) & 1ull) && s_act[lane] > g * 64);
                 if (!blocks_g) break;
-                const GroupDesc G = groups[g];
+                const GroupDesc G = cgroup(groups + g);
                 uint32_t cnt;
                 if (G.tab_bytes <= kGroupTabBudget) {
                     if (*s_staged != (int)g) {
@@ -610,20 +735,27 @@ __device__ void joff_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
     }
 }
 
-// inclusive-exclusive helper: block-wide exclusive prefix of one value per thread
-__device__ __forceinline__ unsigned long long block_excl(unsigned long long v, unsigned long long* s_loc,
+// block-wide exclusive prefix of one value per thread (wave scans + the
+// waves' totals); *total receives the sum over the block
+__device__ __forceinline__ unsigned long long block_excl(unsigned long long v, unsigned long long* s_w,
                                                          unsigned long long* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, (unsigned)o);
+        if (lane >= o) x += y;
+    }
     __syncthreads();
-    s_loc[threadIdx.x] = v;
+    if (lane == 63) s_w[wave] = x;
     __syncthreads();
-    unsigned long long run = 0, all = 0;
-    for (int t = 0; t < kWG; ++t) {
-        const unsigned long long x = s_loc[t];
-        if (t < (int)threadIdx.x) run += x;
-        all += x;
+    unsigned long long pre = 0, all = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        const unsigned long long t = s_w[w];
+        if (w < wave) pre += t;
+        all += t;
     }
     *total = all;
-    return run;
+    return pre + x - v;
 }
 
 __device__ __forceinline__ void put_unit(GACE_GLOBAL AggUnit* u, uint32_t part, uint32_t kind, uint32_t a,
@@ -643,15 +775,19 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
     JoinAcc& acc = a.accs[jd->acc];
     const uint32_t P = 1u << jd->log2P;
     GACE_GLOBAL uint32_t* base = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off);
-    unsigned long long* s_loc = (unsigned long long*)(lds + kLdsMisc);
+    unsigned long long* s_w = (unsigned long long*)(lds + 320);     // kWaves wave totals
+    uint32_t* s_b = (uint32_t*)(lds + kLdsMisc);                    // [2][P + 1] staged in LDS
+    // the per-side partition totals, staged with coalesced loads
+    for (uint32_t i = threadIdx.x; i < 2 * (P + 1); i += kWG) s_b[i] = (i % (P + 1)) < P ? base[i] : 0u;
+    __syncthreads();
     const uint32_t chunk = (P + kWG - 1) / kWG;
     const uint32_t lo = min(P, threadIdx.x * chunk), hi = min(P, lo + chunk);
     unsigned long long tot[2];
     for (int s = 0; s < 2; ++s) {
-        GACE_GLOBAL uint32_t* b = base + (uint64_t)s * (P + 1);
+        uint32_t* b = s_b + s * (P + 1);
         unsigned long long local = 0;
         for (uint32_t i = lo; i < hi; ++i) local += b[i];
-        unsigned long long run = block_excl(local, s_loc, &tot[s]);
+        unsigned long long run = block_excl(local, s_w, &tot[s]);
         for (uint32_t i = lo; i < hi; ++i) {
             const uint32_t v = b[i];
             b[i] = (uint32_t)run;
@@ -660,9 +796,10 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
         if (threadIdx.x == 0) b[P] = (uint32_t)tot[s];
     }
     __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 2 * (P + 1); i += kWG) base[i] = s_b[i];
     // aggregation units
-    const GACE_GLOBAL uint32_t* b0 = base;
-    const GACE_GLOBAL uint32_t* b1 = base + (P + 1);
+    const uint32_t* b0 = s_b;
+    const uint32_t* b1 = s_b + (P + 1);
     unsigned long long n_chunk = 0, n_small = 0, n_split = 0;
     for (uint32_t p = lo; p < hi; ++p) {
         const uint64_t np = (uint64_t)(b0[p + 1] - b0[p]) + (b1[p + 1] - b1[p]);
@@ -674,9 +811,9 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
         }
     }
     unsigned long long t_chunk, t_small, t_split;
-    unsigned long long c_at = block_excl(n_chunk, s_loc, &t_chunk);
-    unsigned long long s_at = block_excl(n_small, s_loc, &t_small) + t_chunk;
-    unsigned long long m_ord = block_excl(n_split, s_loc, &t_split);
+    unsigned long long c_at = block_excl(n_chunk, s_w, &t_chunk);
+    unsigned long long s_at = block_excl(n_small, s_w, &t_small) + t_chunk;
+    unsigned long long m_ord = block_excl(n_split, s_w, &t_split);
     GACE_GLOBAL AggUnit* units = (GACE_GLOBAL AggUnit*)(a.arena_base + jd->units_off);
     GACE_GLOBAL uint32_t* done = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->done_off);
     const bool fits = t_chunk <= jd->max_chunks && t_chunk + t_small + t_split <= jd->max_units;
@@ -742,7 +879,7 @@ struct TileLds {
     uint32_t* cnt;               // [F] tile count per digit
     uint32_t* start;             // [F + 1] tile start per digit; start[F] = keys in the tile
     unsigned long long* key;     // [kTileKeys] keys sorted by digit
-    uint8_t* dig;                // [kTileKeys] their digits
+    uint32_t* dest;              // [kTileKeys] their output index
 };
 
 __device__ __forceinline__ TileLds tile_lds(uint8_t* lds) {
@@ -751,25 +888,31 @@ __device__ __forceinline__ TileLds tile_lds(uint8_t* lds) {
     L.cnt = L.cur + 132;
     L.start = L.cnt + 132;
     L.key = (unsigned long long*)(lds + kLdsMisc + 3 * 132 * 4);
-    L.dig = (uint8_t*)(L.key + kTileKeys);
+    L.dest = (uint32_t*)(L.key + kTileKeys);
     return L;
 }
 
-// digit of a key: (hash >> shift) mod F (F a power of two <= 128)
-__device__ void tile_partition(const uint64_t (&k)[kPer], uint32_t nt, uint32_t shift, uint32_t F,
+// The tile's entries are keys (first pass: hashed here, sentinel keys
+// dropped) or hashes (second pass); the hashes are written out.  Digit of a
+// hash: (hash >> shift) mod F (F a power of two <= 128).  All digits are
+// computed first and the rank atomics issued back to back, so their LDS
+// latencies overlap; each entry's output index is recorded beside it, so the
+// copy-out reads two independent LDS words per entry.
+// L.cnt must be zero on entry (it is again on return).
+template <bool kKeys>
+__device__ void tile_partition(uint64_t (&k)[kPer], uint32_t nt, uint32_t shift, uint32_t F,
                                GACE_GLOBAL int64_t* dst, const TileLds& L) {
-    for (uint32_t i = threadIdx.x; i < F; i += kWG) L.cnt[i] = 0;
-    __syncthreads();
-    uint32_t rd[kPer];   // rank in its digit << 8 | digit, or ~0 for no key
+    uint32_t d[kPer], r[kPer];   // digit (~0: no entry at this position) and rank within it
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const uint32_t pos = threadIdx.x + (uint32_t)u * kWG;
-        rd[u] = ~0u;
-        if (pos < nt && k[u] != kEmptyKey) {
-            const uint32_t d = F > 1 ? (uint32_t)(mix_key(k[u]) >> shift) & (F - 1) : 0u;
-            rd[u] = atomicAdd(&L.cnt[d], 1u) << 8 | d;
-        }
+        const bool ok = pos < nt && (!kKeys || k[u] != kEmptyKey);
+        if (kKeys) k[u] = mix_key(k[u]);
+        const uint32_t dg = F > 1 ? (uint32_t)(k[u] >> shift) & (F - 1) : 0u;
+        d[u] = ok ? dg : ~0u;
     }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) r[u] = d[u] != ~0u ? atomicAdd(&L.cnt[d[u]], 1u) : 0u;
     __syncthreads();
     if (threadIdx.x < 64) {
         const uint32_t lane = threadIdx.x;
@@ -788,21 +931,24 @@ __device__ void tile_partition(const uint64_t (&k)[kPer], uint32_t nt, uint32_t 
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-        if (rd[u] != ~0u) {
-            const uint32_t d = rd[u] & 0xFFu;
-            const uint32_t at = L.start[d] + (rd[u] >> 8);
+        if (d[u] != ~0u) {
+            const uint32_t at = L.start[d[u]] + r[u];
             L.key[at] = k[u];
-            L.dig[at] = (uint8_t)d;
+            L.dest[at] = L.cur[d[u]] + r[u];
         }
     }
     __syncthreads();
     const uint32_t m = L.start[F];
-    for (uint32_t i = threadIdx.x; i < m; i += kWG) {
-        const uint32_t dd = L.dig[i];
-        dst[(uint64_t)L.cur[dd] + (i - L.start[dd])] = (int64_t)L.key[i];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const uint32_t i = threadIdx.x + (uint32_t)u * kWG;
+        if (i < m) dst[L.dest[i]] = (int64_t)L.key[i];
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < F; i += kWG) L.cur[i] += L.cnt[i];
+    for (uint32_t i = threadIdx.x; i < F; i += kWG) {
+        L.cur[i] += L.cnt[i];
+        L.cnt[i] = 0;
+    }
     __syncthreads();
 }
 
@@ -871,7 +1017,10 @@ __device__ void jscatter_item(const BatchArgs& a, const JoinDesc* jd, const Item
         (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off) + (uint64_t)it.side * (P + 1);
     const GACE_GLOBAL uint32_t* row = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off) + (uint64_t)it.sub * P;
     const TileLds L = tile_lds(lds);
-    for (uint32_t i = threadIdx.x; i < F1; i += kWG) L.cur[i] = 0;
+    for (uint32_t i = threadIdx.x; i < F1; i += kWG) {
+        L.cur[i] = 0;
+        L.cnt[i] = 0;
+    }
     __syncthreads();
     for (uint32_t p = threadIdx.x; p < P; p += kWG) atomicAdd(&L.cur[p >> log2P2], row[p]);
     __syncthreads();
@@ -882,7 +1031,7 @@ __device__ void jscatter_item(const BatchArgs& a, const JoinDesc* jd, const Item
                                (it.side ? acc.nkeys[0] : 0ull);
     const uint32_t shift = 64 - log2P1;
     for_each_tile(&jd->side[it.side], it.begin, it.end, lds,
-                  [&](const uint64_t (&k)[kPer], uint32_t nt) { tile_partition(k, nt, shift, F1, dst, L); });
+                  [&](uint64_t (&k)[kPer], uint32_t nt) { tile_partition<true>(k, nt, shift, F1, dst, L); });
 }
 
 // second pass: a unit is one first-pass bucket of a group of consecutive
@@ -918,6 +1067,7 @@ __device__ void jscatter2_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* 
         if (threadIdx.x < 64) {
             const uint32_t q = threadIdx.x;
             uint32_t o0 = 0, o1 = 0;
+            L.cnt[q] = 0;
             if (q < F2) {
                 o0 = rows[(uint64_t)i0 * P + p0 + q];
                 o1 = i1 < iend ? rows[(uint64_t)i1 * P + p0 + q] : base[p0 + q + 1] - base[p0 + q];
@@ -951,7 +1101,7 @@ __device__ void jscatter2_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* 
             const uint32_t nt = (uint32_t)min((uint64_t)kTileKeys, hi - t0);
             const bool more = t0 + kTileKeys < hi;
             if (more) load(t0 + kTileKeys, kn);
-            tile_partition(k, nt, shift, F2, dst, L);
+            tile_partition<false>(k, nt, shift, F2, dst, L);
             if (more) {
 #pragma unroll
                 for (int u2 = 0; u2 < kPer; ++u2) k[u2] = kn[u2];
@@ -978,121 +1128,141 @@ __device__ __forceinline__ void agg_size(AggLds& T, uint64_t n) {
     T.limit = s / 4 * 3;
 }
 
-__device__ __forceinline__ void agg_insert(AggLds& T, uint64_t h, uint64_t key, uint32_t c0, uint32_t c1,
-                                           uint32_t* s_claims, uint32_t* s_over) {
-    const uint32_t mask = T.slots - 1;
-    uint32_t i = (uint32_t)(h >> 20) & mask;
-    for (uint32_t probe = 0; probe < T.slots; ++probe) {
-        unsigned long long k = T.key[i];
-        if (k == kEmptyKey) {
-            if (atomicAdd(s_claims, 1u) >= T.limit) {
-                *s_over = 1;
-                return;
-            }
-            k = atomicCAS(&T.key[i], (unsigned long long)kEmptyKey, (unsigned long long)key);
-            if (k == kEmptyKey) k = key;
-        }
-        if (k == key) {
-            if (c0) atomicAdd(&T.c0[i], c0);
-            if (c1) atomicAdd(&T.c1[i], c1);
-            return;
-        }
-        i = (i + 1) & mask;
-    }
-    *s_over = 1;
-}
-
-// one segment of aggregation input: either bare keys of one side (count 1)
-// or chunk-table entries carrying both counts
-struct AggSeg {
-    const GACE_GLOBAL int64_t* keys;        // bare keys, or nullptr
-    const GACE_GLOBAL MergeEntry* ent;      // chunk-table entries, or nullptr
-    uint64_t n;
-    int side;
-};
-
-// insert one entry per lane (valid lanes only) whose hash lies in residue
-// class res mod m; the first valid lane's key absorbs its duplicates in the
-// wave (Zipf heads)
-__device__ __forceinline__ void agg_entry(AggLds& T, bool bare, uint64_t key, uint32_t c0, uint32_t c1, bool inr,
-                                          uint64_t m, uint64_t res, uint32_t* s_ctl, int lane) {
-    const uint64_t h = mix_key(key);
-    const bool valid = inr && (h & (m - 1)) == res;
-    const unsigned long long vb = __ballot(valid);
-    if (!vb) return;
-    const int lead = __ffsll((long long)vb) - 1;
-    const uint64_t klead = __shfl(key, lead);
-    const unsigned long long eq = __ballot(valid && key == klead);
-    bool go = valid;
-    const int ne = __popcll(eq);
-    if (ne > 1) {
-        const bool mine = (eq >> lane) & 1ull;
-        uint32_t s0, s1;
-        if (bare) {
-            s0 = c0 ? (uint32_t)ne : 0u;
-            s1 = c1 ? (uint32_t)ne : 0u;
-        } else {
-            s0 = mine ? c0 : 0u;
-            s1 = mine ? c1 : 0u;
-            for (int o = 32; o; o >>= 1) {
-                s0 += __shfl_xor(s0, o);
-                s1 += __shfl_xor(s1, o);
-            }
-        }
-        if (mine) {
-            go = lane == lead;
-            c0 = s0;
-            c1 = s1;
-        }
-    }
-    if (go) agg_insert(T, h, key, c0, c1, &s_ctl[0], &s_ctl[1]);
-}
-
-// insert a segment: each lane loads kAggBatch entries before inserting them,
-// so the loads of a batch are in flight together; stops once the pass has
-// overflowed (it will be redone on split residue classes)
+// Insert entries whose hash lies in residue class res mod m.
+// Each lane loads kAggBatch entries, then all of them probe together: every
+// step issues the pending entries' slot reads at once, then their claims of
+// empty slots (compare-and-swap) at once, so a step costs two LDS round
+// trips for all of them.  Claimed slots are counted once per wave; past 3/4
+// of the table the pass is abandoned (the spare quarter absorbs the keys
+// inserted before the count catches up) and redone on split residue classes;
+// so is a pass that finds the table full.
 constexpr int kAggBatch = 4;
-__device__ __forceinline__ void agg_segment(AggLds& T, const AggSeg& sg, uint64_t m, uint64_t res, uint32_t* s_ctl) {
+
+// probe kAggBatch entries per lane into the table (see above); counts the
+// wave's claimed slots and flags an overflow in s_ctl[1]
+__device__ __forceinline__ void agg_probe(AggLds& T, const uint64_t (&h)[kAggBatch], const uint32_t (&c0)[kAggBatch],
+                                          const uint32_t (&c1)[kAggBatch], uint64_t m, uint64_t res,
+                                          uint32_t* s_ctl) {
     const int lane = threadIdx.x & 63;
-    const bool bare = sg.keys != nullptr;
-    const uint32_t b0 = sg.side == 0, b1 = sg.side == 1;
-    for (uint64_t e0 = 0; e0 < sg.n; e0 += (uint64_t)kWG * kAggBatch) {
+    const uint32_t mask = T.slots - 1;
+    uint32_t slot[kAggBatch];
+    bool pend[kAggBatch];
+#pragma unroll
+    for (int u = 0; u < kAggBatch; ++u) {
+        pend[u] = h[u] != kEmptyHash && (h[u] & (m - 1)) == res;
+        slot[u] = (uint32_t)(h[u] >> 20) & mask;
+    }
+    uint32_t took = 0;
+    for (uint32_t probe = 0;; ++probe) {
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < kAggBatch; ++u) any |= pend[u];
+        if (!__ballot(any)) break;
+        if (probe > mask) {              // every slot probed: the table is full
+            s_ctl[1] = 1;
+            break;
+        }
+        unsigned long long cur[kAggBatch];
+#pragma unroll
+        for (int u = 0; u < kAggBatch; ++u) cur[u] = pend[u] ? T.key[slot[u]] : 0ull;
+#pragma unroll
+        for (int u = 0; u < kAggBatch; ++u)
+            if (pend[u] && cur[u] == kEmptyHash) {
+                cur[u] = atomicCAS(&T.key[slot[u]], (unsigned long long)kEmptyHash, (unsigned long long)h[u]);
+                if (cur[u] == kEmptyHash) {
+                    cur[u] = h[u];
+                    ++took;
+                }
+            }
+#pragma unroll
+        for (int u = 0; u < kAggBatch; ++u)
+            if (pend[u]) {
+                if (cur[u] == h[u]) {
+                    if (c0[u]) atomicAdd(&T.c0[slot[u]], c0[u]);
+                    if (c1[u]) atomicAdd(&T.c1[slot[u]], c1[u]);
+                    pend[u] = false;
+                } else {
+                    slot[u] = (slot[u] + 1) & mask;
+                }
+            }
+    }
+    uint32_t wt = took;
+    for (int o = 32; o; o >>= 1) wt += __shfl_xor(wt, o);
+    if (lane == 0 && wt && atomicAdd(&s_ctl[0], wt) + wt > T.limit) s_ctl[1] = 1;
+}
+
+// chunk-table entries (merge units): one batch at a time
+__device__ __forceinline__ void agg_entries(AggLds& T, const GACE_GLOBAL MergeEntry* ent, uint64_t n, uint64_t m,
+                                            uint64_t res, uint32_t* s_ctl) {
+    for (uint64_t e0 = 0; e0 < n; e0 += (uint64_t)kWG * kAggBatch) {
         if (__hip_atomic_load(&s_ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
-        uint64_t key[kAggBatch];
+        uint64_t h[kAggBatch];
         uint32_t c0[kAggBatch], c1[kAggBatch];
 #pragma unroll
         for (int u = 0; u < kAggBatch; ++u) {
             const uint64_t e = e0 + (uint64_t)u * kWG + threadIdx.x;
-            key[u] = 0;
-            c0[u] = 0;
-            c1[u] = 0;
-            if (e < sg.n) {
-                if (bare) {
-                    key[u] = (uint64_t)__builtin_nontemporal_load(sg.keys + e);
-                    c0[u] = b0;
-                    c1[u] = b1;
-                } else {
-                    key[u] = sg.ent[e].key;
-                    c0[u] = sg.ent[e].c0;
-                    c1[u] = sg.ent[e].c1;
-                }
-            }
+            h[u] = e < n ? ent[e].key : kEmptyHash;
+            c0[u] = e < n ? ent[e].c0 : 0u;
+            c1[u] = e < n ? ent[e].c1 : 0u;
         }
-#pragma unroll
-        for (int u = 0; u < kAggBatch; ++u)
-            agg_entry(T, bare, key[u], c0[u], c1[u], e0 + (uint64_t)u * kWG + threadIdx.x < sg.n, m, res, s_ctl,
-                      lane);
+        agg_probe(T, h, c0, c1, m, res, s_ctl);
     }
 }
 
-// aggregate the segments exactly: residue classes of the hash are split until
-// each class's distinct keys fit one LDS table.  emit == nullptr: add NDV and
-// join partials to n0, n1, jn; else write each table entry to emit (count in
-// *s_emit).
-template <typename SegAt>
-__device__ void aggregate(AggLds& T, uint32_t nseg, SegAt&& seg_at, uint32_t* s_ctl, uint32_t* stack,
+// bare hashes of a unit: nR of side R then nS of side S, as one stream whose
+// next batch is loaded while the current one probes
+__device__ __forceinline__ void agg_bare(AggLds& T, const GACE_GLOBAL int64_t* hr, uint64_t nR,
+                                         const GACE_GLOBAL int64_t* hs, uint64_t nS, uint64_t m, uint64_t res,
+                                         uint32_t* s_ctl) {
+    const uint64_t total = nR + nS;
+    auto load = [&](uint64_t e0, uint64_t (&h)[kAggBatch]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < kAggBatch; ++u) {
+            const uint64_t e = e0 + (uint64_t)u * kWG + threadIdx.x;
+            h[u] = e < nR ? (uint64_t)__builtin_nontemporal_load(hr + e)
+                          : (e < total ? (uint64_t)__builtin_nontemporal_load(hs + (e - nR)) : kEmptyHash);
+        }
+    };
+    if (total == 0) return;
+    uint64_t h[kAggBatch], hn[kAggBatch];
+    load(0, h);
+    for (uint64_t e0 = 0; e0 < total; e0 += (uint64_t)kWG * kAggBatch) {
+        if (__hip_atomic_load(&s_ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+        const uint64_t e1 = e0 + (uint64_t)kWG * kAggBatch;
+        if (e1 < total) load(e1, hn);
+        uint32_t c0[kAggBatch], c1[kAggBatch];
+#pragma unroll
+        for (int u = 0; u < kAggBatch; ++u) {
+            const uint64_t e = e0 + (uint64_t)u * kWG + threadIdx.x;
+            c0[u] = e < nR ? 1u : 0u;
+            c1[u] = e < nR ? 0u : 1u;
+        }
+        agg_probe(T, h, c0, c1, m, res, s_ctl);
+        if (e1 < total) {
+#pragma unroll
+            for (int u = 0; u < kAggBatch; ++u) h[u] = hn[u];
+        }
+    }
+}
+
+// The LDS table is clean (every slot empty, counts zero) whenever no pass is
+// running: a pass that completes resets each slot as it reads it out, one
+// that overflows clears the slots it used.  The worker clears the whole
+// region once before its first unit.
+__device__ __forceinline__ void agg_clear(AggLds& T, uint32_t slots) {
+    for (uint32_t i = threadIdx.x; i < slots; i += kWG) {
+        T.key[i] = kEmptyHash;
+        T.c0[i] = 0;
+        T.c1[i] = 0;
+    }
+}
+
+// pass(m, res) inserts every entry of the unit in residue class res mod m
+template <typename Pass>
+__device__ void aggregate(AggLds& T, Pass&& pass, uint32_t* s_ctl, uint32_t* stack,
                           GACE_GLOBAL MergeEntry* emit, unsigned long long& n0, unsigned long long& n1,
-                          unsigned long long& jn, JoinAcc& acc) {
+                          unsigned long long& jn, JoinAcc& acc, uint32_t& passes) {
+    const int lane = threadIdx.x & 63;
     if (threadIdx.x == 0) {
         stack[0] = 1;
         stack[1] = 0;
@@ -1110,16 +1280,13 @@ __device__ void aggregate(AggLds& T, uint32_t nseg, SegAt&& seg_at, uint32_t* s_
             s_ctl[0] = 0;
             s_ctl[1] = 0;
         }
-        for (uint32_t i = threadIdx.x; i < T.slots; i += kWG) {
-            T.key[i] = kEmptyKey;
-            T.c0[i] = 0;
-            T.c1[i] = 0;
-        }
         __syncthreads();
         const uint64_t m = s_ctl[4], res = s_ctl[5];
-        for (uint32_t g = 0; g < nseg; ++g) agg_segment(T, seg_at(g), m, res, s_ctl);
+        ++passes;
+        pass(m, res);
         __syncthreads();
         if (s_ctl[1]) {
+            agg_clear(T, T.slots);
             if (threadIdx.x == 0) {
                 const uint32_t sp = s_ctl[3];
                 if (m < (1u << 20) && sp + 2 <= 64) {
@@ -1134,16 +1301,34 @@ __device__ void aggregate(AggLds& T, uint32_t nseg, SegAt&& seg_at, uint32_t* s_
                 }
             }
         } else {
-            for (uint32_t i = threadIdx.x; i < T.slots; i += kWG) {
-                const unsigned long long k = T.key[i];
-                if (k == kEmptyKey) continue;
-                const uint32_t x = T.c0[i], y = T.c1[i];
+            for (uint32_t i0 = 0; i0 < T.slots; i0 += kWG) {
+                const uint32_t i = i0 + threadIdx.x;
+                unsigned long long k = kEmptyHash;
+                uint32_t x = 0, y = 0;
+                if (i < T.slots) {
+                    k = T.key[i];
+                    x = T.c0[i];
+                    y = T.c1[i];
+                    if (k != kEmptyHash) {
+                        T.key[i] = kEmptyHash;
+                        T.c0[i] = 0;
+                        T.c1[i] = 0;
+                    }
+                }
+                const bool full = k != kEmptyHash;
                 if (emit) {
-                    const uint32_t at = atomicAdd(&s_ctl[6], 1u);
-                    emit[at].key = k;
-                    emit[at].c0 = x;
-                    emit[at].c1 = y;
-                } else {
+                    // one slot claim per wave for its entries
+                    const unsigned long long fb = __ballot(full);
+                    uint32_t base = 0;
+                    if (lane == 0 && fb) base = atomicAdd(&s_ctl[6], (uint32_t)__popcll(fb));
+                    base = __shfl(base, 0);
+                    if (full) {
+                        const uint32_t at = base + (uint32_t)__popcll(fb & ((1ull << lane) - 1ull));
+                        emit[at].key = k;
+                        emit[at].c0 = x;
+                        emit[at].c1 = y;
+                    }
+                } else if (full) {
                     n0 += x != 0;
                     n1 += y != 0;
                     jn += (unsigned long long)x * y;
@@ -1154,7 +1339,9 @@ __device__ void aggregate(AggLds& T, uint32_t nseg, SegAt&& seg_at, uint32_t* s_
     }
 }
 
-__device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds) {
+// work: aggregation units taken << 32 | table passes made
+__device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds, uint64_t& work) {
+    uint32_t n_taken = 0, passes = 0;
     JoinAcc& acc = a.accs[jd->acc];
     const uint32_t P = 1u << jd->log2P;
     unsigned long long* s_red = (unsigned long long*)(lds + 320);
@@ -1175,12 +1362,16 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
     const GACE_GLOBAL int64_t* bufS = bufR + acc.nkeys[0];
     GACE_GLOBAL MergeEntry* merge = (GACE_GLOBAL MergeEntry*)(a.arena_base + acc.merge_off);
     const uint32_t n_units = acc.n_units;
+    if (!dead) agg_clear(T, kAggSlots);
+    // thread 0 claims the next unit while the current one is aggregated
+    uint32_t claim_next = 0;
+    if (threadIdx.x == 0) s_ctl[2] = dead ? ~0u : atomicAdd(&acc.next_unit, 1u);
+    __syncthreads();
     while (!dead) {
-        if (threadIdx.x == 0) s_ctl[2] = atomicAdd(&acc.next_unit, 1u);
-        __syncthreads();
         const uint32_t u = s_ctl[2];
         __syncthreads();
         if (u >= n_units) break;
+        if (threadIdx.x == 0) claim_next = atomicAdd(&acc.next_unit, 1u);
         AggUnit U;
         U.part = units[u].part;
         U.kind = units[u].kind;
@@ -1199,16 +1390,15 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
             __threadfence();
             agg_size(T, (uint64_t)kAggSlots);
             aggregate(
-                T, U.b,
-                [&](uint32_t c) {
-                    AggSeg sg;
-                    sg.keys = nullptr;
-                    sg.ent = merge + (uint64_t)(U.a + c) * kChunkKeys;
-                    sg.n = chunk_cnt[U.a + c];
-                    sg.side = 0;
-                    return sg;
+                T,
+                [&](uint64_t m, uint64_t res) {
+                    for (uint32_t c = 0; c < U.b; ++c)
+                        agg_entries(T, merge + (uint64_t)(U.a + c) * kChunkKeys, chunk_cnt[U.a + c], m, res, s_ctl);
                 },
-                s_ctl, stack, nullptr, n0, n1, jn, acc);
+                s_ctl, stack, nullptr, n0, n1, jn, acc, passes);
+            ++n_taken;
+            if (threadIdx.x == 0) s_ctl[2] = claim_next;
+            __syncthreads();
             continue;
         }
         uint64_t lo = 0, hi = nR + nS;
@@ -1216,36 +1406,28 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
             lo = (uint64_t)U.a * kChunkKeys;
             hi = min(hi, lo + kChunkKeys);
         }
-        // the unit's keys: [lo, hi) of the partition's R keys followed by its S keys
-        auto seg_at = [&](uint32_t g) {
-            AggSeg sg;
-            sg.ent = nullptr;
-            const bool has_r = lo < nR;
-            if (g == 0 && has_r) {
-                sg.keys = bufR + bR + lo;
-                sg.n = min(hi, nR) - lo;
-                sg.side = 0;
-            } else {
-                const uint64_t s0 = lo > nR ? lo - nR : 0;
-                sg.keys = bufS + bS + s0;
-                sg.n = hi > nR ? (hi - nR) - s0 : 0;
-                sg.side = 1;
-            }
-            return sg;
+        // the unit's entries: [lo, hi) of the partition's R hashes followed by its S hashes
+        const uint64_t r0 = lo < nR ? lo : nR, r1 = hi < nR ? hi : nR;
+        const uint64_t s0 = lo > nR ? lo - nR : 0, s1 = hi > nR ? hi - nR : 0;
+        auto pass = [&](uint64_t m, uint64_t res) {
+            agg_bare(T, bufR + bR + r0, r1 - r0, bufS + bS + s0, s1 - s0, m, res, s_ctl);
         };
-        const uint32_t nseg = (lo < nR ? 1u : 0u) + (hi > nR ? 1u : 0u);
         agg_size(T, hi - lo);
         if (U.kind == AU_CHUNK) {
-            aggregate(T, nseg, seg_at, s_ctl, stack, merge + (uint64_t)U.b * kChunkKeys, n0, n1, jn, acc);
+            aggregate(T, pass, s_ctl, stack, merge + (uint64_t)U.b * kChunkKeys, n0, n1, jn, acc, passes);
             if (threadIdx.x == 0) {
                 chunk_cnt[U.b] = s_ctl[6];
                 __threadfence();
                 atomicAdd(&done[U.ord], 1u);
             }
         } else {
-            aggregate(T, nseg, seg_at, s_ctl, stack, nullptr, n0, n1, jn, acc);
+            aggregate(T, pass, s_ctl, stack, nullptr, n0, n1, jn, acc, passes);
         }
+        ++n_taken;
+        if (threadIdx.x == 0) s_ctl[2] = claim_next;
+        __syncthreads();
     }
+    work = (uint64_t)n_taken << 32 | passes;
     jn = block_sum(jn, s_red);
     n0 = block_sum(n0, s_red);
     n1 = block_sum(n1, s_red);
@@ -1309,7 +1491,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 8))
 }
 
 // join phases (queue 1: items [n_scan_items, n_items), in phase order)
-__global__ void __launch_bounds__(kWG) gace_join_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))) gace_join_kernel(BatchArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ uint32_t s_item;
     const PlanHdr H = *(const PlanHdr*)a.plan;
@@ -1317,7 +1499,7 @@ __global__ void __launch_bounds__(kWG) gace_join_kernel(BatchArgs a) {
         const uint32_t idx = pop_item(&a.head[1], H.n_scan_items, &s_item);
         if (idx >= H.n_items) break;
         const uint64_t t0 = (uint64_t)wall_clock64();
-        uint64_t t1 = t0;
+        uint64_t t1 = t0, work = 0;
         const Item it = a.items[idx];
         const JoinDesc* jd = (const JoinDesc*)(a.plan + H.joins_off) + it.idx;
         JoinAcc& acc = a.accs[jd->acc];
@@ -1356,13 +1538,13 @@ __global__ void __launch_bounds__(kWG) gace_join_kernel(BatchArgs a) {
                 else
                     wait_count(&acc.scatter_done, jd->n_items);
                 t1 = (uint64_t)wall_clock64();
-                jagg_item(a, jd, it, lds);
+                jagg_item(a, jd, it, lds, work);
                 break;
             default:
                 break;
         }
         __syncthreads();
-        trace_item(a, H, idx, it, t0, t1);
+        trace_item(a, H, idx, it, t0, t1, work);
     }
 }
 

@@ -18,7 +18,12 @@ constexpr uint32_t kMaxPredsPerReq = 65536;
 constexpr uint64_t kThrAll = 1ull << 32;               // threshold meaning "keep every block"
 constexpr uint32_t kLutMaxEntries = 2048;              // LUT programs up to this many entries
 constexpr uint32_t kGroupTabBudget = 40u << 10;        // group tables staged in LDS up to this size
-constexpr uint64_t kEmptyKey = 0x8000000000000000ull;  // LDS table sentinel (INT64_MIN), counted out of band
+constexpr uint64_t kEmptyKey = 0x8000000000000000ull;  // sentinel key (INT64_MIN), counted out of band
+// Partition buffers and aggregation tables hold the 64-bit MurmurHash3
+// finalizer of each key instead of the key: the finalizer is a bijection, so
+// equal hashes mean equal keys.  The sentinel key's hash marks empty slots
+// (no partitioned entry can carry it).
+constexpr uint64_t kEmptyHash = 0x8f780810af31a493ull;
 constexpr uint32_t kPartBitsMax = 13;                  // at most 8192 hash partitions per join
 constexpr uint32_t kAggSlots = 4096;                   // LDS key-table slots of one aggregation pass, at most
 constexpr uint32_t kAggMinSlots = 256;                 // ... and at least (a unit sizes its table to its keys)
@@ -46,7 +51,7 @@ struct PlanHdr {
 struct TraceRec {
     uint32_t kind, index, wg, xcc;
     uint64_t t_begin, t_ready, t_end;   // steady-counter ticks: popped, dependencies met, done
-    uint64_t reserved;
+    uint64_t work;                      // item-specific: aggregation units << 32 | table passes
 };
 
 // one shared pass over one table's kept blocks
@@ -130,7 +135,7 @@ struct AggUnit {
 
 // entry of a chunk table handed to the merge
 struct MergeEntry {
-    uint64_t key;
+    uint64_t key;            // the key's hash
     uint32_t c0, c1;
 };
 
