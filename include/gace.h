@@ -174,8 +174,9 @@ typedef struct {
     uint32_t item_rows;        /* target sampled rows per work item */
     uint32_t count_mode;       /* 0 auto, 1 ballot, 2 transpose */
     uint32_t join_part_keys;   /* expected sampled keys per join hash partition (power of two) */
-    uint32_t join_wgs_per_cu;  /* join kernel grid = CUs * join_wgs_per_cu */
-    uint32_t reserved[2];
+    uint32_t join_wgs_per_cu;  /* join partitioning kernel grid = CUs * join_wgs_per_cu */
+    uint32_t agg_wgs_per_cu;   /* join aggregation kernel grid = CUs * agg_wgs_per_cu */
+    uint32_t reserved;
 } gace_schedule;
 
 /* ---------------------------------------------------------------- context */
@@ -232,10 +233,11 @@ gace_status gace_last_batch_stats(gace_ctx* ctx, double* kernel_ms, uint64_t* al
 
 /* Per-kernel timing of the last gace_batch_run that ran by direct launch
    (gace_set_graph(ctx, 0)): device time of the scan kernel, measured with HIP
-   events on the call's stream, and of the join kernel, measured on the
-   context's side stream where it runs concurrently; with the algorithmic HBM
-   bytes of each (scan: kept rows x referenced column widths per shared scan;
-   join: 8 bytes per sampled key + 16 bytes per distinct key and side).
+   events on the call's stream, and of the join stage (the partitioning
+   kernel followed by the aggregation kernel), measured on the context's side
+   stream where it runs concurrently; with the algorithmic HBM bytes of each
+   (scan: kept rows x referenced column widths per shared scan; join: 8 bytes
+   per sampled key + 16 bytes per distinct key and side).
    timed = 0 and both times 0 after a graph-replayed batch. */
 typedef struct {
     double scan_ms, join_ms;

@@ -81,7 +81,8 @@ class gace_request(ctypes.Structure):
 class gace_schedule(ctypes.Structure):
     _fields_ = [("wg_threads", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32), ("item_rows", ctypes.c_uint32),
                 ("count_mode", ctypes.c_uint32), ("join_part_keys", ctypes.c_uint32),
-                ("join_wgs_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+                ("join_wgs_per_cu", ctypes.c_uint32), ("agg_wgs_per_cu", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class gace_trace_rec(ctypes.Structure):
@@ -397,7 +398,8 @@ def gace_get_schedule(ctx: int) -> dict:
     s = gace_schedule()
     _check(lib().gace_get_schedule(ctx, ctypes.byref(s)))
     return dict(wg_threads=s.wg_threads, wgs_per_cu=s.wgs_per_cu, item_rows=s.item_rows,
-                count_mode=s.count_mode, join_part_keys=s.join_part_keys, join_wgs_per_cu=s.join_wgs_per_cu)
+                count_mode=s.count_mode, join_part_keys=s.join_part_keys, join_wgs_per_cu=s.join_wgs_per_cu,
+                agg_wgs_per_cu=s.agg_wgs_per_cu)
 
 
 def gace_set_schedule(ctx: int, **kw):

@@ -703,12 +703,16 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     std::stable_sort(scan_items.begin(), scan_items.end(), [&](const Item& x, const Item& y) {
         return scans[x.idx].row_bytes * scans[x.idx].thr_max > scans[y.idx].row_bytes * scans[y.idx].thr_max;
     });
-    // scans form the first queue; the join queue follows in phase order, so a
-    // join item only ever waits for items earlier in its queue
+    // scans form the first queue; the join partitioning queue follows in
+    // phase order, so a join item only ever waits for items earlier in its
+    // queue; the aggregation queue comes last (its kernel runs after the
+    // partitioning kernel on the same stream)
     out.items.insert(out.items.end(), scan_items.begin(), scan_items.end());
     const uint32_t n_scan_items = (uint32_t)out.items.size();
-    for (auto* v : {&hist_items, &off_items, &base_items, &scatter_items, &scatter2_items, &agg_items})
+    for (auto* v : {&hist_items, &off_items, &base_items, &scatter_items, &scatter2_items})
         out.items.insert(out.items.end(), v->begin(), v->end());
+    const uint32_t n_join_end = (uint32_t)out.items.size();
+    out.items.insert(out.items.end(), agg_items.begin(), agg_items.end());
 
     // ---- plan blob
     PlanHdr H;
@@ -721,6 +725,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     H.n_hist = n_hist;
     H.n_items = (uint32_t)out.items.size();
     H.n_scan_items = n_scan_items;
+    H.n_join_end = n_join_end;
     H.arena_static = arena_static;
     std::vector<uint8_t>& blob = out.plan;
     {

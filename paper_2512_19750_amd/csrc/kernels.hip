@@ -32,11 +32,10 @@ constexpr uint32_t kLdsThr = kScanLdsHist * 8 + 640;                            
 constexpr uint32_t kLdsBytes = kLdsMisc + kLdsCnt + kLdsHist + kLdsThr + kGroupTabBudget;   // scan kernel
 constexpr int kPer = kTileKeys / kWG;                                              // staged keys per thread
 constexpr uint32_t kTileLdsBytes = 3 * 132 * 4 + kTileKeys * 12;                     // cursors, counts, starts, tile
-constexpr uint32_t kAggLdsBytes = kAggSlots * 16 + 512;                             // key table + split stack
 constexpr uint32_t kBaseLdsBytes = 2 * ((1u << kPartBitsMax) + 1) * 4;                 // staged partition starts
 constexpr uint32_t lds_max(uint32_t x, uint32_t y) { return x > y ? x : y; }
 constexpr uint32_t kJoinLdsBytes =
-    kLdsMisc + lds_max(lds_max(kTileLdsBytes, kAggLdsBytes), lds_max(kBaseLdsBytes, (1u << kPartBitsMax) * 4));
+    kLdsMisc + lds_max(kTileLdsBytes, lds_max(kBaseLdsBytes, (1u << kPartBitsMax) * 4));
 
 // explicit address spaces: pointers read from the plan are generic to the
 // compiler; global loads through them must not become flat loads, which would
@@ -51,14 +50,14 @@ constexpr uint32_t kJoinLdsBytes =
 struct BatchArgs {
     const uint8_t* plan;
     const Item* items;
-    uint32_t* head;            // [0] scan queue, [1] join queue
+    uint32_t* head;            // [0] scan queue, [1] join partitioning queue, [2] aggregation queue
     unsigned long long* counts;
     unsigned long long* hist;
     JoinAcc* accs;
     uint8_t* arena_base;       // join tables and partition buffers
     Arena* arena;
     uint32_t count_mode;       // 0 auto, 1 ballot, 2 transpose
-    uint32_t reserved;
+    uint32_t agg_slots;        // aggregation kernel: LDS table slots (power of two)
     TraceRec* trace;           // one record per item when the plan asks for tracing
 };
 
@@ -632,10 +631,12 @@ __device__ __forceinline__ void for_each_sampled_key(const JoinSide* D, uint64_t
             const uint64_t r1 = (r0 + B < n) ? r0 + B : n;
             for (uint64_t r = r0 + threadIdx.x; r < r1; r += 8 * kWG) {
                 uint64_t k[8];
+                // unconditional loads (clamped in range): no branch makes the
+                // wave wait for one load before issuing the next
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const uint64_t rr = r + (uint64_t)u * kWG;
-                    k[u] = rr < r1 ? (uint64_t)__builtin_nontemporal_load(keys + rr) : 0ull;
+                    k[u] = (uint64_t)__builtin_nontemporal_load(keys + (rr < r1 ? rr : r1 - 1));
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
@@ -977,15 +978,15 @@ __device__ void for_each_tile(const JoinSide* D, uint64_t b0, uint64_t b1, uint8
             const uint64_t last = (cb + s_kidx[c - 1]) << log2B;
             const uint64_t total = (uint64_t)(c - 1) * B + min(B, n - last);
             // the next tile's keys are loaded while this tile is partitioned
+            // positions past the end are clamped to the last one (loads stay
+            // unconditional); the partitioner ignores them
             auto load = [&](uint64_t t0, uint64_t (&k)[kPer]) {
 #pragma unroll
                 for (int u = 0; u < kPer; ++u) {
-                    const uint64_t pos = t0 + threadIdx.x + (uint64_t)u * kWG;
-                    k[u] = 0;
-                    if (pos < total) {
-                        const uint64_t row = ((cb + s_kidx[pos >> log2B]) << log2B) + (pos & (B - 1));
-                        k[u] = (uint64_t)__builtin_nontemporal_load(keys + row);
-                    }
+                    uint64_t pos = t0 + threadIdx.x + (uint64_t)u * kWG;
+                    pos = pos < total ? pos : total - 1;
+                    const uint64_t row = ((cb + s_kidx[pos >> log2B]) << log2B) + (pos & (B - 1));
+                    k[u] = (uint64_t)__builtin_nontemporal_load(keys + row);
                 }
             };
             uint64_t k[kPer], kn[kPer];
@@ -1092,7 +1093,7 @@ __device__ void jscatter2_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* 
 #pragma unroll
             for (int u2 = 0; u2 < kPer; ++u2) {
                 const uint64_t pos = t0 + threadIdx.x + (uint64_t)u2 * kWG;
-                k[u2] = pos < hi ? (uint64_t)__builtin_nontemporal_load(src + pos) : 0ull;
+                k[u2] = (uint64_t)__builtin_nontemporal_load(src + (pos < hi ? pos : hi - 1));
             }
         };
         uint64_t k[kPer], kn[kPer];
@@ -1120,10 +1121,10 @@ struct AggLds {
 };
 
 // table size for a unit of n entries: a power of two with n <= 3/4 of it when
-// it fits, so a unit of at most 3/4 kAggSlots entries never overflows
-__device__ __forceinline__ void agg_size(AggLds& T, uint64_t n) {
+// it fits, so a unit of at most 3/4 of the largest table never overflows
+__device__ __forceinline__ void agg_size(AggLds& T, uint64_t n, uint32_t cap) {
     uint32_t s = kAggMinSlots;
-    while (s < kAggSlots && (uint64_t)s * 3 < n * 4) s <<= 1;
+    while (s < cap && (uint64_t)s * 3 < n * 4) s <<= 1;
     T.slots = s;
     T.limit = s / 4 * 3;
 }
@@ -1138,19 +1139,23 @@ __device__ __forceinline__ void agg_size(AggLds& T, uint64_t n) {
 // so is a pass that finds the table full.
 constexpr int kAggBatch = 4;
 
-// probe kAggBatch entries per lane into the table (see above); counts the
-// wave's claimed slots and flags an overflow in s_ctl[1]
+// Probe kAggBatch entries per lane into the table.  Slots are paired into
+// buckets read with one 16-byte LDS load: an entry matches either slot of
+// its bucket, or claims the bucket's first empty slot, or, when the bucket
+// is full of other hashes, moves to the next bucket (slots only ever fill,
+// so a hash is always in the first bucket that had room for it).  Counts
+// the wave's claimed slots and flags an overflow in s_ctl[1].
 __device__ __forceinline__ void agg_probe(AggLds& T, const uint64_t (&h)[kAggBatch], const uint32_t (&c0)[kAggBatch],
                                           const uint32_t (&c1)[kAggBatch], uint64_t m, uint64_t res,
                                           uint32_t* s_ctl) {
     const int lane = threadIdx.x & 63;
-    const uint32_t mask = T.slots - 1;
-    uint32_t slot[kAggBatch];
+    const uint32_t nb = T.slots / 2, bmask = nb - 1;
+    uint32_t bk[kAggBatch];
     bool pend[kAggBatch];
 #pragma unroll
     for (int u = 0; u < kAggBatch; ++u) {
-        pend[u] = h[u] != kEmptyHash && (h[u] & (m - 1)) == res;
-        slot[u] = (uint32_t)(h[u] >> 20) & mask;
+        pend[u] = (c0[u] | c1[u]) != 0u && (h[u] & (m - 1)) == res;
+        bk[u] = (uint32_t)(h[u] >> 20) & bmask;
     }
     uint32_t took = 0;
     for (uint32_t probe = 0;; ++probe) {
@@ -1158,32 +1163,53 @@ __device__ __forceinline__ void agg_probe(AggLds& T, const uint64_t (&h)[kAggBat
 #pragma unroll
         for (int u = 0; u < kAggBatch; ++u) any |= pend[u];
         if (!__ballot(any)) break;
-        if (probe > mask) {              // every slot probed: the table is full
+        if (probe >= nb) {               // every bucket probed: the table is full
             s_ctl[1] = 1;
             break;
         }
-        unsigned long long cur[kAggBatch];
-#pragma unroll
-        for (int u = 0; u < kAggBatch; ++u) cur[u] = pend[u] ? T.key[slot[u]] : 0ull;
+        u64x2 cur[kAggBatch];
 #pragma unroll
         for (int u = 0; u < kAggBatch; ++u)
-            if (pend[u] && cur[u] == kEmptyHash) {
-                cur[u] = atomicCAS(&T.key[slot[u]], (unsigned long long)kEmptyHash, (unsigned long long)h[u]);
-                if (cur[u] == kEmptyHash) {
-                    cur[u] = h[u];
+            cur[u] = pend[u] ? *(const u64x2*)(T.key + 2 * bk[u]) : u64x2{0ull, 0ull};
+        int at[kAggBatch];
+#pragma unroll
+        for (int u = 0; u < kAggBatch; ++u) {
+            at[u] = -1;
+            if (!pend[u]) continue;
+            if (cur[u].x == h[u]) {
+                at[u] = 0;
+            } else if (cur[u].y == h[u]) {
+                at[u] = 1;
+            } else if (cur[u].x == kEmptyHash || cur[u].y == kEmptyHash) {
+                const int t = cur[u].x == kEmptyHash ? 0 : 1;
+                unsigned long long o =
+                    atomicCAS(&T.key[2 * bk[u] + t], (unsigned long long)kEmptyHash, (unsigned long long)h[u]);
+                if (o == kEmptyHash) {
+                    at[u] = t;
                     ++took;
+                } else if (o == h[u]) {
+                    at[u] = t;
+                } else if (t == 0 && cur[u].y == kEmptyHash) {
+                    o = atomicCAS(&T.key[2 * bk[u] + 1], (unsigned long long)kEmptyHash, (unsigned long long)h[u]);
+                    if (o == kEmptyHash) {
+                        at[u] = 1;
+                        ++took;
+                    } else if (o == h[u]) {
+                        at[u] = 1;
+                    }
                 }
+                // a lost claim re-reads the same bucket next step
+            } else {
+                bk[u] = (bk[u] + 1) & bmask;   // bucket full of other hashes
             }
+        }
 #pragma unroll
         for (int u = 0; u < kAggBatch; ++u)
-            if (pend[u]) {
-                if (cur[u] == h[u]) {
-                    if (c0[u]) atomicAdd(&T.c0[slot[u]], c0[u]);
-                    if (c1[u]) atomicAdd(&T.c1[slot[u]], c1[u]);
-                    pend[u] = false;
-                } else {
-                    slot[u] = (slot[u] + 1) & mask;
-                }
+            if (pend[u] && at[u] >= 0) {
+                const uint32_t sl = 2 * bk[u] + (uint32_t)at[u];
+                if (c0[u]) atomicAdd(&T.c0[sl], c0[u]);
+                if (c1[u]) atomicAdd(&T.c1[sl], c1[u]);
+                pend[u] = false;
             }
     }
     uint32_t wt = took;
@@ -1215,12 +1241,15 @@ __device__ __forceinline__ void agg_bare(AggLds& T, const GACE_GLOBAL int64_t* h
                                          const GACE_GLOBAL int64_t* hs, uint64_t nS, uint64_t m, uint64_t res,
                                          uint32_t* s_ctl) {
     const uint64_t total = nR + nS;
+    // one unconditional load per entry (positions past the end are clamped
+    // to the last entry and carry zero counts)
     auto load = [&](uint64_t e0, uint64_t (&h)[kAggBatch]) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < kAggBatch; ++u) {
-            const uint64_t e = e0 + (uint64_t)u * kWG + threadIdx.x;
-            h[u] = e < nR ? (uint64_t)__builtin_nontemporal_load(hr + e)
-                          : (e < total ? (uint64_t)__builtin_nontemporal_load(hs + (e - nR)) : kEmptyHash);
+            uint64_t e = e0 + (uint64_t)u * kWG + threadIdx.x;
+            e = e < total ? e : total - 1;
+            const GACE_GLOBAL int64_t* p = e < nR ? hr + e : hs + (e - nR);
+            h[u] = (uint64_t)__builtin_nontemporal_load(p);
         }
     };
     if (total == 0) return;
@@ -1235,7 +1264,7 @@ __device__ __forceinline__ void agg_bare(AggLds& T, const GACE_GLOBAL int64_t* h
         for (int u = 0; u < kAggBatch; ++u) {
             const uint64_t e = e0 + (uint64_t)u * kWG + threadIdx.x;
             c0[u] = e < nR ? 1u : 0u;
-            c1[u] = e < nR ? 0u : 1u;
+            c1[u] = e >= nR && e < total ? 1u : 0u;
         }
         agg_probe(T, h, c0, c1, m, res, s_ctl);
         if (e1 < total) {
@@ -1347,10 +1376,11 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
     unsigned long long* s_red = (unsigned long long*)(lds + 320);
     uint32_t* s_ctl = (uint32_t*)(lds + 352);   // [0] claims [1] over [2] unit [3] sp [4] m [5] r [6] emitted
     AggLds T;
+    const uint32_t cap = a.agg_slots;
     T.key = (unsigned long long*)(lds + kLdsMisc);
-    T.c0 = (uint32_t*)(lds + kLdsMisc + kAggSlots * 8);
-    T.c1 = (uint32_t*)(lds + kLdsMisc + kAggSlots * 12);
-    uint32_t* stack = (uint32_t*)(lds + kLdsMisc + kAggSlots * 16);   // 64 x (m, r)
+    T.c0 = (uint32_t*)(lds + kLdsMisc + cap * 8);
+    T.c1 = (uint32_t*)(lds + kLdsMisc + cap * 12);
+    uint32_t* stack = (uint32_t*)(lds + kLdsMisc + cap * 16);   // 64 x (m, r)
     const GACE_GLOBAL uint32_t* base0 = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off);
     const GACE_GLOBAL uint32_t* base1 = base0 + (P + 1);
     const GACE_GLOBAL AggUnit* units = (const GACE_GLOBAL AggUnit*)(a.arena_base + jd->units_off);
@@ -1362,7 +1392,7 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
     const GACE_GLOBAL int64_t* bufS = bufR + acc.nkeys[0];
     GACE_GLOBAL MergeEntry* merge = (GACE_GLOBAL MergeEntry*)(a.arena_base + acc.merge_off);
     const uint32_t n_units = acc.n_units;
-    if (!dead) agg_clear(T, kAggSlots);
+    if (!dead) agg_clear(T, a.agg_slots);
     // thread 0 claims the next unit while the current one is aggregated
     uint32_t claim_next = 0;
     if (threadIdx.x == 0) s_ctl[2] = dead ? ~0u : atomicAdd(&acc.next_unit, 1u);
@@ -1388,7 +1418,7 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
             }
             __syncthreads();
             __threadfence();
-            agg_size(T, (uint64_t)kAggSlots);
+            agg_size(T, (uint64_t)a.agg_slots, a.agg_slots);
             aggregate(
                 T,
                 [&](uint64_t m, uint64_t res) {
@@ -1412,7 +1442,7 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
         auto pass = [&](uint64_t m, uint64_t res) {
             agg_bare(T, bufR + bR + r0, r1 - r0, bufS + bS + s0, s1 - s0, m, res, s_ctl);
         };
-        agg_size(T, hi - lo);
+        agg_size(T, hi - lo, a.agg_slots);
         if (U.kind == AU_CHUNK) {
             aggregate(T, pass, s_ctl, stack, merge + (uint64_t)U.b * kChunkKeys, n0, n1, jn, acc, passes);
             if (threadIdx.x == 0) {
@@ -1497,7 +1527,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))
     const PlanHdr H = *(const PlanHdr*)a.plan;
     for (;;) {
         const uint32_t idx = pop_item(&a.head[1], H.n_scan_items, &s_item);
-        if (idx >= H.n_items) break;
+        if (idx >= H.n_join_end) break;
         const uint64_t t0 = (uint64_t)wall_clock64();
         uint64_t t1 = t0, work = 0;
         const Item it = a.items[idx];
@@ -1532,19 +1562,30 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))
                 jscatter2_item(a, jd, lds);
                 signal_count(&acc.s2_done);
                 break;
-            case IT_JAGG:
-                if (jd->log2P2)
-                    wait_count(&acc.s2_done, jd->n_s2);
-                else
-                    wait_count(&acc.scatter_done, jd->n_items);
-                t1 = (uint64_t)wall_clock64();
-                jagg_item(a, jd, it, lds, work);
-                break;
             default:
                 break;
         }
         __syncthreads();
         trace_item(a, H, idx, it, t0, t1, work);
+    }
+}
+
+// join aggregation (queue 2: items [n_join_end, n_items)); launched after
+// the partitioning kernel on the same stream, so every partition is final
+__global__ void __launch_bounds__(kWG) gace_agg_kernel(BatchArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    __shared__ uint32_t s_item;
+    const PlanHdr H = *(const PlanHdr*)a.plan;
+    for (;;) {
+        const uint32_t idx = pop_item(&a.head[2], H.n_join_end, &s_item);
+        if (idx >= H.n_items) break;
+        const uint64_t t0 = (uint64_t)wall_clock64();
+        uint64_t work = 0;
+        const Item it = a.items[idx];
+        const JoinDesc* jd = (const JoinDesc*)(a.plan + H.joins_off) + it.idx;
+        jagg_item(a, jd, it, lds, work);
+        __syncthreads();
+        trace_item(a, H, idx, it, t0, t0, work);
     }
 }
 
@@ -1563,6 +1604,7 @@ __global__ void __launch_bounds__(kWG) gace_init_kernel(const uint8_t* plan, uin
     if (tid == 0) {
         head[0] = 0;
         head[1] = 0;
+        head[2] = 0;
         arena->used = H.arena_static;
     }
 }
@@ -1583,6 +1625,13 @@ hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hi
 hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream) {
     const gace::BatchArgs& a = *(const gace::BatchArgs*)args;
     hipLaunchKernelGGL(gace::gace_scan_kernel, dim3(grid), dim3(gace::kWG), gace::kLdsBytes, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t gace_launch_agg(const void* args, uint32_t grid, hipStream_t stream) {
+    const gace::BatchArgs& a = *(const gace::BatchArgs*)args;
+    const uint32_t lds = gace::kLdsMisc + a.agg_slots * 16 + 512;
+    hipLaunchKernelGGL(gace::gace_agg_kernel, dim3(grid), dim3(gace::kWG), lds, stream, a);
     return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ struct PlanHdr {
     uint32_t n_counts, n_hist, n_items, n_scan_items;   // items [0, n_scan_items) are scans
     uint64_t arena_static;   // bytes of the arena holding the joins' per-item tables
     uint32_t trace;          // nonzero: kernels write one TraceRec per item
-    uint32_t reserved2;
+    uint32_t n_join_end;     // items [n_scan_items, n_join_end) are join partitioning items, the rest aggregation
 };
 
 // per-item trace record (same layout as gace_trace_rec)

@@ -21,6 +21,7 @@ hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hi
                             hipStream_t stream);
 hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream);
 hipError_t gace_launch_join(const void* args, uint32_t grid, hipStream_t stream);
+hipError_t gace_launch_agg(const void* args, uint32_t grid, hipStream_t stream);
 }
 
 namespace gace {
@@ -36,7 +37,7 @@ struct BatchArgsHost {
     uint8_t* arena_base;
     Arena* arena;
     uint32_t count_mode;
-    uint32_t reserved;
+    uint32_t agg_slots;
     TraceRec* trace;
 };
 
@@ -62,15 +63,24 @@ static gace_schedule default_schedule() {
     s.item_rows = 131072;
     s.count_mode = 0;
     s.join_part_keys = 1024;
-    s.join_wgs_per_cu = 4;
+    s.join_wgs_per_cu = 2;
+    s.agg_wgs_per_cu = 3;
     return s;
 }
 
 static bool valid_schedule(const gace_schedule& s) {
     const uint32_t pk = s.join_part_keys;
     return s.wg_threads == 256 && s.wgs_per_cu >= 1 && s.wgs_per_cu <= 8 && s.join_wgs_per_cu >= 1 &&
-           s.join_wgs_per_cu <= 4 && s.item_rows >= 1024 &&
+           s.join_wgs_per_cu <= 4 && s.agg_wgs_per_cu >= 1 && s.agg_wgs_per_cu <= 8 && s.item_rows >= 1024 &&
            s.count_mode <= 2 && pk >= 128 && pk <= 65536 && (pk & (pk - 1)) == 0;
+}
+
+// LDS table size of the aggregation kernel: room for about 1.5x the expected
+// keys of a partition at 3/4 load
+static uint32_t agg_slots(const gace_schedule& s) {
+    uint32_t slots = 1024;
+    while (slots < 4096 && slots < 2 * s.join_part_keys) slots <<= 1;
+    return slots;
 }
 
 static BatchArgsHost make_args(gace_ctx* c) {
@@ -84,13 +94,14 @@ static BatchArgsHost make_args(gace_ctx* c) {
     a.arena_base = c->d_arena_base;
     a.arena = c->d_arena;
     a.count_mode = c->sched.count_mode;
-    a.reserved = 0;
+    a.agg_slots = agg_slots(c->sched);
     a.trace = c->d_trace;
     return a;
 }
 
 static uint32_t scan_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.wgs_per_cu; }
 static uint32_t join_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.join_wgs_per_cu; }
+static uint32_t agg_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.agg_wgs_per_cu; }
 
 // init kernel, then the scan kernel on st and the join kernel on the side
 // stream concurrently (they touch disjoint state), joined back into st
@@ -101,6 +112,7 @@ static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, 
     HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
     if (timed) HIP_TRY(hipEventRecord(c->ev_j0, side), "event");
     HIP_TRY(gace_launch_join(&a, join_grid(c), side), "join kernel");
+    HIP_TRY(gace_launch_agg(&a, agg_grid(c), side), "aggregation kernel");
     if (timed) {
         HIP_TRY(hipEventRecord(c->ev_j1, side), "event");
         HIP_TRY(hipEventRecord(c->ev_s0, st), "event");
@@ -540,7 +552,8 @@ static std::string sched_json(const gace_schedule& s) {
     std::ostringstream os;
     os << "{\"wg_threads\": " << s.wg_threads << ", \"wgs_per_cu\": " << s.wgs_per_cu
        << ", \"item_rows\": " << s.item_rows << ", \"count_mode\": " << s.count_mode
-       << ", \"join_part_keys\": " << s.join_part_keys << ", \"join_wgs_per_cu\": " << s.join_wgs_per_cu << "}";
+       << ", \"join_part_keys\": " << s.join_part_keys << ", \"join_wgs_per_cu\": " << s.join_wgs_per_cu
+       << ", \"agg_wgs_per_cu\": " << s.agg_wgs_per_cu << "}";
     return os.str();
 }
 
@@ -571,6 +584,7 @@ static void load_cache(gace_ctx* c, const char* path, const std::string& prefix)
         parse_u32(line, "count_mode", s.count_mode);
         parse_u32(line, "join_part_keys", s.join_part_keys);
         parse_u32(line, "join_wgs_per_cu", s.join_wgs_per_cu);
+        parse_u32(line, "agg_wgs_per_cu", s.agg_wgs_per_cu);
         if (valid_schedule(s)) c->tuned[key.substr(prefix.size())] = s;
     }
 }
@@ -633,6 +647,7 @@ gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, c
     const uint32_t modes[] = {0, 1, 2};
     const uint32_t parts[] = {512, 1024, 2048};
     const uint32_t jwgs[] = {1, 2, 3, 4};
+    const uint32_t awgs[] = {1, 2, 3, 4};
     for (int pass = 0; pass < 2; ++pass) {
         for (uint32_t v : wgs) {
             gace_schedule s = best; s.wgs_per_cu = v; double ms;
@@ -652,6 +667,10 @@ gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, c
         }
         for (uint32_t v : jwgs) {
             gace_schedule s = best; s.join_wgs_per_cu = v; double ms;
+            if (time_it(s, ms) == GACE_OK && ms < best_ms) { best = s; best_ms = ms; }
+        }
+        for (uint32_t v : awgs) {
+            gace_schedule s = best; s.agg_wgs_per_cu = v; double ms;
             if (time_it(s, ms) == GACE_OK && ms < best_ms) { best = s; best_ms = ms; }
         }
     }
