@@ -689,20 +689,44 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     }
 
     // ---- items
+    // A kept block streams predicate group g only when its draw is below the
+    // threshold of the first request owning a bit of g, so a scan's work per
+    // kept row is its row width times the expected groups per kept block.
+    // Items are sized to about item_rows rows of one group each and queued
+    // costliest first, so the tail of the queue is short items.
     std::vector<Item> scan_items;
+    std::vector<double> item_cost;
     for (uint32_t s = 0; s < scans.size(); ++s) {
         const ScanDesc& S = scans[s];
-        const uint64_t bb = bpi_for(S.thr_max, S.log2B, opt.item_rows);
+        const uint32_t* rc = rcum_flat.data() + S.req_begin;
+        const uint64_t* rt = rthr_flat.data() + S.req_begin;
+        double gpb = 0.0;
+        uint32_t k = 0;
+        for (uint64_t g = 0; 64 * g < rc[S.n_req]; ++g) {
+            while (k + 1 <= S.n_req && rc[k + 1] <= 64 * g) ++k;
+            gpb += S.thr_max ? (double)rt[k] / (double)S.thr_max : 0.0;
+        }
+        if (gpb < 1.0) gpb = 1.0;
+        const uint32_t rows = std::max<uint32_t>(1024u, (uint32_t)((double)opt.item_rows / gpb));
+        const uint64_t bb = bpi_for(S.thr_max, S.log2B, rows);
         if (bb == 0) continue;
+        const double p = S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0;
         for (uint64_t b = 0; b < S.n_blocks; b += bb) {
             Item it = {IT_SCAN, s, 0, 0, b, std::min(S.n_blocks, b + bb)};
             scan_items.push_back(it);
+            item_cost.push_back((double)(it.end - it.begin) * (double)(1ull << S.log2B) * p * S.row_bytes * gpb);
         }
     }
-    // larger scans first so the tail of the queue is short items
-    std::stable_sort(scan_items.begin(), scan_items.end(), [&](const Item& x, const Item& y) {
-        return scans[x.idx].row_bytes * scans[x.idx].thr_max > scans[y.idx].row_bytes * scans[y.idx].thr_max;
-    });
+    {
+        std::vector<uint32_t> order(scan_items.size());
+        for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t x, uint32_t y) { return item_cost[x] > item_cost[y]; });
+        std::vector<Item> sorted;
+        sorted.reserve(order.size());
+        for (uint32_t i : order) sorted.push_back(scan_items[i]);
+        scan_items.swap(sorted);
+    }
     // scans form the first queue; the join partitioning queue follows in
     // phase order, so a join item only ever waits for items earlier in its
     // queue; the aggregation queue comes last (its kernel runs after the
