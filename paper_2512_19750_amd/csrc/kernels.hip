@@ -32,7 +32,7 @@ constexpr uint32_t kLdsThr = kScanLdsHist * 8 + 640;                            
 constexpr uint32_t kLdsBytes = kLdsMisc + kLdsCnt + kLdsHist + kLdsThr + kGroupTabBudget;   // scan kernel
 constexpr int kPer = kTileKeys / kWG;                                              // staged keys per thread
 constexpr uint32_t kTileLdsBytes = 3 * 132 * 4 + kTileKeys * 12;                     // cursors, counts, starts, tile
-constexpr uint32_t kBaseLdsBytes = 2 * ((1u << kPartBitsMax) + 1) * 4;                 // staged partition starts
+constexpr uint32_t kBaseLdsBytes = ((1u << kPartBitsMax) + 1) * 4;                     // one side's partition starts
 constexpr uint32_t lds_max(uint32_t x, uint32_t y) { return x > y ? x : y; }
 constexpr uint32_t kJoinLdsBytes =
     kLdsMisc + lds_max(kTileLdsBytes, lds_max(kBaseLdsBytes, (1u << kPartBitsMax) * 4));
@@ -772,38 +772,50 @@ __device__ __forceinline__ void put_unit(GACE_GLOBAL AggUnit* u, uint32_t part, 
 // totals, the partition buffer and chunk tables carved from the arena, and
 // the list of aggregation units: partitions with more than kChunkKeys keys
 // are split into chunks followed by one merge unit
+// exclusive prefix of s_b[0..P) in place (contiguous chunks per thread);
+// s_b[P] receives the total, which is also returned
+__device__ __forceinline__ unsigned long long lds_prefix(uint32_t* s_b, uint32_t P, unsigned long long* s_w) {
+    const uint32_t chunk = (P + kWG - 1) / kWG;
+    const uint32_t lo = min(P, threadIdx.x * chunk), hi = min(P, lo + chunk);
+    unsigned long long local = 0, tot = 0;
+    for (uint32_t i = lo; i < hi; ++i) local += s_b[i];
+    unsigned long long run = block_excl(local, s_w, &tot);
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t v = s_b[i];
+        s_b[i] = (uint32_t)run;
+        run += v;
+    }
+    if (threadIdx.x == 0) s_b[P] = (uint32_t)tot;
+    __syncthreads();
+    return tot;
+}
+
+// Partition starts per side (exclusive prefix of the totals), per-side key
+// totals, the partition buffers and chunk tables carved from the arena, and
+// the list of aggregation units: partitions with more than kChunkKeys keys
+// are split into chunks followed by one merge unit.  One side's starts are
+// staged in LDS at a time; the units are counted while side 1's starts are
+// in LDS and side 0 still holds its totals in global memory.
 __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds) {
     JoinAcc& acc = a.accs[jd->acc];
     const uint32_t P = 1u << jd->log2P;
     GACE_GLOBAL uint32_t* base = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off);
+    GACE_GLOBAL uint32_t* b0 = base;               // side 0: totals, then starts
+    GACE_GLOBAL uint32_t* b1 = base + (P + 1);     // side 1
     unsigned long long* s_w = (unsigned long long*)(lds + 320);     // kWaves wave totals
-    uint32_t* s_b = (uint32_t*)(lds + kLdsMisc);                    // [2][P + 1] staged in LDS
-    // the per-side partition totals, staged with coalesced loads
-    for (uint32_t i = threadIdx.x; i < 2 * (P + 1); i += kWG) s_b[i] = (i % (P + 1)) < P ? base[i] : 0u;
-    __syncthreads();
-    const uint32_t chunk = (P + kWG - 1) / kWG;
-    const uint32_t lo = min(P, threadIdx.x * chunk), hi = min(P, lo + chunk);
+    uint32_t* s_b = (uint32_t*)(lds + kLdsMisc);                    // [P + 1] staged in LDS
     unsigned long long tot[2];
-    for (int s = 0; s < 2; ++s) {
-        uint32_t* b = s_b + s * (P + 1);
-        unsigned long long local = 0;
-        for (uint32_t i = lo; i < hi; ++i) local += b[i];
-        unsigned long long run = block_excl(local, s_w, &tot[s]);
-        for (uint32_t i = lo; i < hi; ++i) {
-            const uint32_t v = b[i];
-            b[i] = (uint32_t)run;
-            run += v;
-        }
-        if (threadIdx.x == 0) b[P] = (uint32_t)tot[s];
-    }
+    // side 1 starts
+    for (uint32_t i = threadIdx.x; i < P; i += kWG) s_b[i] = b1[i];
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < 2 * (P + 1); i += kWG) base[i] = s_b[i];
-    // aggregation units
-    const uint32_t* b0 = s_b;
-    const uint32_t* b1 = s_b + (P + 1);
+    tot[1] = lds_prefix(s_b, P, s_w);
+    for (uint32_t i = threadIdx.x; i <= P; i += kWG) b1[i] = s_b[i];
+    // aggregation units (partitions interleaved over threads: coalesced reads;
+    // the unit order only needs chunks, then whole partitions, then merges)
+    auto np_of = [&](uint32_t p) { return (uint64_t)b0[p] + (s_b[p + 1] - s_b[p]); };
     unsigned long long n_chunk = 0, n_small = 0, n_split = 0;
-    for (uint32_t p = lo; p < hi; ++p) {
-        const uint64_t np = (uint64_t)(b0[p + 1] - b0[p]) + (b1[p + 1] - b1[p]);
+    for (uint32_t p = threadIdx.x; p < P; p += kWG) {
+        const uint64_t np = np_of(p);
         if (np > kChunkKeys) {
             n_chunk += (np + kChunkKeys - 1) / kChunkKeys;
             n_split += 1;
@@ -819,8 +831,8 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
     GACE_GLOBAL uint32_t* done = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->done_off);
     const bool fits = t_chunk <= jd->max_chunks && t_chunk + t_small + t_split <= jd->max_units;
     if (fits) {
-        for (uint32_t p = lo; p < hi; ++p) {
-            const uint64_t np = (uint64_t)(b0[p + 1] - b0[p]) + (b1[p + 1] - b1[p]);
+        for (uint32_t p = threadIdx.x; p < P; p += kWG) {
+            const uint64_t np = np_of(p);
             if (np > kChunkKeys) {
                 const uint32_t nc = (uint32_t)((np + kChunkKeys - 1) / kChunkKeys);
                 for (uint32_t c = 0; c < nc; ++c)
@@ -835,6 +847,12 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
             }
         }
     }
+    __syncthreads();
+    // side 0 starts
+    for (uint32_t i = threadIdx.x; i < P; i += kWG) s_b[i] = b0[i];
+    __syncthreads();
+    tot[0] = lds_prefix(s_b, P, s_w);
+    for (uint32_t i = threadIdx.x; i <= P; i += kWG) b0[i] = s_b[i];
     // per-side sampled and sentinel key counts from the histogram items
     {
         const GACE_GLOBAL unsigned long long* st =
@@ -930,20 +948,42 @@ __device__ void tile_partition(uint64_t (&k)[kPer], uint32_t nt, uint32_t shift,
         if (lane == 63) L.start[F] = x;
     }
     __syncthreads();
+    // all LDS reads of a step are issued before any dependent write, so their
+    // latencies overlap (indices are clamped in range; writes stay guarded)
+    {
+        uint32_t st[kPer], cu[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        if (d[u] != ~0u) {
-            const uint32_t at = L.start[d[u]] + r[u];
-            L.key[at] = k[u];
-            L.dest[at] = L.cur[d[u]] + r[u];
+        for (int u = 0; u < kPer; ++u) {
+            const uint32_t dd = d[u] != ~0u ? d[u] : 0u;
+            st[u] = L.start[dd];
+            cu[u] = L.cur[dd];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            if (d[u] != ~0u) {
+                const uint32_t at = st[u] + r[u];
+                L.key[at] = k[u];
+                L.dest[at] = cu[u] + r[u];
+            }
         }
     }
     __syncthreads();
-    const uint32_t m = L.start[F];
+    {
+        const uint32_t m = L.start[F];
+        uint32_t de[kPer];
+        unsigned long long kk[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const uint32_t i = threadIdx.x + (uint32_t)u * kWG;
-        if (i < m) dst[L.dest[i]] = (int64_t)L.key[i];
+        for (int u = 0; u < kPer; ++u) {
+            const uint32_t i = threadIdx.x + (uint32_t)u * kWG;
+            const uint32_t ic = i < m ? i : 0u;
+            de[u] = L.dest[ic];
+            kk[u] = L.key[ic];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const uint32_t i = threadIdx.x + (uint32_t)u * kWG;
+            if (i < m) dst[de[u]] = (int64_t)kk[u];
+        }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < F; i += kWG) {
@@ -1065,7 +1105,9 @@ __device__ void jscatter2_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* 
         const GACE_GLOBAL uint32_t* base = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off) +
                                            (uint64_t)side * (P + 1);
         const uint32_t p0 = b << log2P2;
-        if (threadIdx.x < 64) {
+        // F2 <= 128 sub-partitions: one per thread of the first two waves,
+        // each wave's sums of the group's start and end offsets in s_ctl[4..7]
+        if (threadIdx.x < 128) {
             const uint32_t q = threadIdx.x;
             uint32_t o0 = 0, o1 = 0;
             L.cnt[q] = 0;
@@ -1078,16 +1120,17 @@ __device__ void jscatter2_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* 
                 o0 += __shfl_xor(o0, o);
                 o1 += __shfl_xor(o1, o);
             }
-            if (q == 0) {
-                s_ctl[4] = o0;
-                s_ctl[5] = o1;
+            if ((q & 63) == 0) {
+                s_ctl[4 + 2 * (q >> 6)] = o0;
+                s_ctl[5 + 2 * (q >> 6)] = o1;
             }
         }
         __syncthreads();
         const uint64_t side_off = side ? acc.nkeys[0] : 0ull;
         const GACE_GLOBAL int64_t* src = (const GACE_GLOBAL int64_t*)(a.arena_base + acc.tmp_off) + side_off;
         GACE_GLOBAL int64_t* dst = (GACE_GLOBAL int64_t*)(a.arena_base + acc.buf_off) + side_off;
-        const uint64_t lo = (uint64_t)base[p0] + s_ctl[4], hi = (uint64_t)base[p0] + s_ctl[5];
+        const uint64_t lo = (uint64_t)base[p0] + s_ctl[4] + s_ctl[6];
+        const uint64_t hi = (uint64_t)base[p0] + s_ctl[5] + s_ctl[7];
         __syncthreads();
         auto load = [&](uint64_t t0, uint64_t (&k)[kPer]) {
 #pragma unroll

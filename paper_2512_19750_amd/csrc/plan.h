@@ -30,6 +30,10 @@ constexpr uint32_t kAggMinSlots = 256;                 // ... and at least (a un
 constexpr uint32_t kChunkKeys = 1u << 17;              // a partition with more keys is split into chunks + merge
 constexpr uint32_t kTileKeys = 4096;                   // keys staged in LDS per partitioning tile
 constexpr uint32_t kPass1BitsMax = 7;                  // first-pass fan-out at most 128 buckets
+// a fan-out of 2^b partitions is split into 2^(b - b/2) first-pass buckets
+// of 2^(b/2) partitions; both passes partition at most 128 ways
+static_assert(kPartBitsMax - kPartBitsMax / 2 <= kPass1BitsMax && kPartBitsMax / 2 <= 7,
+              "partition passes wider than 128 ways");
 constexpr uint32_t kUnit2Keys = 1u << 17;              // target keys per second-pass unit
 
 // column program kinds
