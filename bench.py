@@ -124,6 +124,47 @@ def cpu_baseline(w, budget_rows_preds: float, nthreads: int):
 
 
 # ---------------------------------------------------------------- serving
+def gate_measurement(g, ctx, sel_reqs, sel_obs):
+    """The decision layer on the measured plain-path probes: the cost model
+    fitted to their latencies (how well it predicts them), the cost of a gate
+    evaluation, and the latency of a probe answered from the result cache
+    against the probe itself."""
+    m = g.gace_cost_create(0.85, 4096)
+    try:
+        feats = []
+        for q, (nrow, ms) in zip(sel_reqs, sel_obs):
+            _, row_bytes, terms = g.gace_cost_features_of(q)
+            feats.append((nrow, row_bytes, terms, ms))
+            g.gace_cost_observe(m, nrow, row_bytes, terms, ms)
+        coef, n_obs = g.gace_cost_coef(m)
+        rel = sorted(abs(g.gace_cost_predict(m, n, b, t) - ms) / ms for n, b, t, ms in feats)
+    finally:
+        g.gace_cost_destroy(m)
+    t0 = time.perf_counter()
+    k = 20000
+    for i in range(k):
+        g.gace_gate_evaluate(ndv=(1000.0, 700.0 + i % 600), sel=(0.1, i % 300, 1000), pcs=(i % 50, 50, 60, 1000))
+    eval_us = (time.perf_counter() - t0) / k * 1e6
+    c = g.gace_cache_create(1 << 20)
+    cold, warm = [], []
+    try:
+        for q in sel_reqs[:64]:
+            for lst in (cold, warm):
+                s = time.perf_counter()
+                g.gace_probe_selectivity_cached(ctx, c, q.table, q.preds, q.seed, q.rate, q.block_rows)
+                lst.append((time.perf_counter() - s) * 1e3)
+        st = g.gace_cache_stats_get(c)
+    finally:
+        g.gace_cache_destroy(c)
+    return {"cost_model": {"coef_ms": [coef[0], coef[1], coef[2]],
+                           "terms": ["fixed", "per byte read", "per row-term"], "observations": n_obs,
+                           "rel_error_p50": round(rel[len(rel) // 2], 4),
+                           "rel_error_p90": round(rel[int(0.9 * (len(rel) - 1))], 4)},
+            "gate_eval_us": round(eval_us, 3),
+            "cache": {"probe_ms_p50": round(_pct(cold, 0.5), 4), "hit_ms_p50": round(_pct(warm, 0.5), 4),
+                      "hits": st["hits"], "misses": st["misses"]}}
+
+
 def _pct(xs, q):
     if not xs:
         return None
@@ -425,9 +466,11 @@ def main():
                                  per_kernel["gace_join_stage"]["ms"], graph_ms, value), file=sys.stderr, flush=True)
 
     plain = None
+    gate = None
     expect = []
     if args.plain:
         lat = []
+        sel_obs = []                      # (sampled rows, row bytes, terms, ms) of each selectivity probe
         t0 = time.perf_counter()
         for q in reqs:
             s = time.perf_counter()
@@ -438,6 +481,8 @@ def main():
                 c, nrow, nblk = g.gace_probe_selectivity(ctx, q.table, q.preds, q.seed, q.rate, q.block_rows)
                 expect.append((tuple(int(x) for x in c), nrow, nblk))
             lat.append((time.perf_counter() - s) * 1e3)
+            if not isinstance(q, g.JoinRequest):
+                sel_obs.append((nrow, lat[-1]))
         plain_s = time.perf_counter() - t0
         lat.sort()
         plain = dict(ms_per_batch=round(plain_s * 1e3, 3), batched_speedup=round(plain_s * 1e3 / ms_step, 3),
@@ -445,6 +490,8 @@ def main():
                      latency_ms_p99=round(lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)], 4))
         print("[bench] plain path %.1f ms (x%.2f)" % (plain_s * 1e3, plain["batched_speedup"]), file=sys.stderr,
               flush=True)
+        gate = gate_measurement(g, ctx, [q for q in reqs if not isinstance(q, g.JoinRequest)], sel_obs)
+        print("[bench] gate %s" % json.dumps(gate), file=sys.stderr, flush=True)
     sched = g.gace_get_schedule(ctx)
     g.gace_destroy(ctx)
     # served: the same requests arriving as an open-loop Poisson stream
@@ -511,6 +558,7 @@ def main():
         "join_keys_per_s": join_keys / (wall / args.steps),
         "served": served,
         "plain_path": plain,
+        "gate": gate,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -107,6 +107,38 @@ class gace_server_stats(ctypes.Structure):
                                                 "inflight", "workspace_in_use", "workspace_peak")]
 
 
+# gace_gate.h
+GATE_DRIFT, GATE_SELERR, GATE_PCS, GATE_PCS_HI, GATE_PCS_LO = 1, 2, 4, 4, 8
+
+
+class gace_gate_cfg(ctypes.Structure):
+    _fields_ = [("drift_min", ctypes.c_double), ("sel_err_max", ctypes.c_double),
+                ("pcs_hi_num", ctypes.c_uint32), ("pcs_hi_den", ctypes.c_uint32),
+                ("pcs_lo_num", ctypes.c_uint32), ("pcs_lo_den", ctypes.c_uint32)]
+
+
+class gace_gate_in(ctypes.Structure):
+    _fields_ = [("have", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("ndv_hist", ctypes.c_double),
+                ("ndv_est", ctypes.c_double), ("s_est", ctypes.c_double), ("count", ctypes.c_uint64),
+                ("n", ctypes.c_uint64), ("c_ab", ctypes.c_uint64), ("c_a", ctypes.c_uint64),
+                ("c_b", ctypes.c_uint64), ("n_pcs", ctypes.c_uint64)]
+
+
+class gace_gate_out(ctypes.Structure):
+    _fields_ = [("drift", ctypes.c_double), ("sel_err", ctypes.c_double), ("pcs", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("undefined", ctypes.c_uint32), ("trigger", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class gace_cost_features(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_double), ("row_bytes", ctypes.c_double), ("terms", ctypes.c_double),
+                ("reserved", ctypes.c_double)]
+
+
+class gace_cache_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("hits", "misses", "inserts", "evictions", "invalidated", "entries")]
+
+
 ABI_FUNCTIONS = [
     "gace_create", "gace_destroy", "gace_last_error", "gace_version", "gace_check_request",
     "gace_probe_selectivity", "gace_join_freq", "gace_batch_run", "gace_autotune", "gace_get_schedule",
@@ -114,6 +146,12 @@ ABI_FUNCTIONS = [
     "gace_set_trace", "gace_get_trace",
     "gace_server_create", "gace_server_submit",
     "gace_server_wait", "gace_server_wait_times", "gace_server_stats_get", "gace_server_destroy",
+    # gace_gate.h
+    "gace_gate_default_cfg", "gace_gate_evaluate", "gace_probe_pcs",
+    "gace_cost_create", "gace_cost_destroy", "gace_cost_observe", "gace_cost_coef", "gace_cost_predict",
+    "gace_cost_features_of", "gace_cost_breakeven",
+    "gace_cache_create", "gace_cache_destroy", "gace_cache_lookup", "gace_cache_insert", "gace_cache_invalidate",
+    "gace_cache_stats_get", "gace_probe_selectivity_cached", "gace_join_freq_cached",
 ]
 
 _lib = None
@@ -161,6 +199,35 @@ def lib():
                                         ctypes.POINTER(u64)], i32),
             "gace_server_stats_get": ([P, ctypes.POINTER(gace_server_stats)], i32),
             "gace_server_destroy": ([P], i32),
+            "gace_gate_default_cfg": ([ctypes.POINTER(gace_gate_cfg)], i32),
+            "gace_gate_evaluate": ([ctypes.POINTER(gace_gate_cfg), ctypes.POINTER(gace_gate_in),
+                                    ctypes.POINTER(gace_gate_out)], i32),
+            "gace_probe_pcs": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
+                                ctypes.POINTER(gace_sample_spec), ctypes.POINTER(gace_gate_in), P], i32),
+            "gace_cost_create": ([ctypes.c_double, u32, ctypes.POINTER(P)], i32),
+            "gace_cost_destroy": ([P], i32),
+            "gace_cost_observe": ([P, ctypes.POINTER(gace_cost_features), ctypes.c_double], i32),
+            "gace_cost_coef": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u32)], i32),
+            "gace_cost_predict": ([P, ctypes.POINTER(gace_cost_features), ctypes.POINTER(ctypes.c_double)], i32),
+            "gace_cost_features_of": ([ctypes.POINTER(gace_request), ctypes.POINTER(gace_cost_features)], i32),
+            "gace_cost_breakeven": ([P, P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
+                                    i32),
+            "gace_cache_create": ([u64, ctypes.POINTER(P)], i32),
+            "gace_cache_destroy": ([P], i32),
+            "gace_cache_lookup": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
+                                   ctypes.POINTER(gace_sample_spec), ctypes.POINTER(u64),
+                                   ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(gace_probe_info),
+                                   ctypes.POINTER(u32)], i32),
+            "gace_cache_insert": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
+                                   ctypes.POINTER(gace_sample_spec), ctypes.POINTER(u64),
+                                   ctypes.POINTER(gace_probe_info)], i32),
+            "gace_cache_invalidate": ([P, u32], i32),
+            "gace_cache_stats_get": ([P, ctypes.POINTER(gace_cache_stats)], i32),
+            "gace_probe_selectivity_cached": ([P, P, ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
+                                               ctypes.POINTER(gace_sample_spec), ctypes.POINTER(u64),
+                                               ctypes.POINTER(gace_probe_info), ctypes.POINTER(u32), P], i32),
+            "gace_join_freq_cached": ([P, P, ctypes.POINTER(gace_keys), ctypes.POINTER(gace_keys),
+                                       ctypes.POINTER(gace_join_result), ctypes.POINTER(u32), P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -501,3 +568,176 @@ def gace_server_stats_get(srv: int) -> dict:
 
 def gace_server_destroy(srv: int):
     _check(lib().gace_server_destroy(srv))
+
+
+# ---------------------------------------------------------------- gace_gate.h
+def gace_gate_default_cfg() -> gace_gate_cfg:
+    c = gace_gate_cfg()
+    _check(lib().gace_gate_default_cfg(ctypes.byref(c)))
+    return c
+
+
+def gace_gate_evaluate(cfg: Optional[gace_gate_cfg] = None, ndv=None, sel=None, pcs=None) -> dict:
+    """ndv = (ndv_hist, ndv_est); sel = (s_est, count, n); pcs = (c_ab, c_a, c_b, n) or a
+    gace_gate_in filled by gace_probe_pcs.  Omitted signals are not evaluated."""
+    if cfg is None:
+        cfg = gace_gate_default_cfg()
+    x = gace_gate_in()
+    if ndv is not None:
+        x.have |= GATE_DRIFT
+        x.ndv_hist, x.ndv_est = float(ndv[0]), float(ndv[1])
+    if sel is not None:
+        x.have |= GATE_SELERR
+        x.s_est, x.count, x.n = float(sel[0]), int(sel[1]), int(sel[2])
+    if isinstance(pcs, gace_gate_in):
+        x.have |= GATE_PCS
+        x.c_ab, x.c_a, x.c_b, x.n_pcs = pcs.c_ab, pcs.c_a, pcs.c_b, pcs.n_pcs
+    elif pcs is not None:
+        x.have |= GATE_PCS
+        x.c_ab, x.c_a, x.c_b, x.n_pcs = (int(v) for v in pcs)
+    o = gace_gate_out()
+    _check(lib().gace_gate_evaluate(ctypes.byref(cfg), ctypes.byref(x), ctypes.byref(o)))
+    return dict(drift=o.drift, sel_err=o.sel_err, pcs=o.pcs, flags=int(o.flags), undefined=int(o.undefined),
+                trigger=bool(o.trigger))
+
+
+def gace_probe_pcs(ctx: int, table: Table, a_terms, b_terms, seed: int = 0, rate: float = 1.0,
+                   block_rows: int = 4096, stream=None) -> gace_gate_in:
+    """One probe of {A, B, A AND B}; returns the gate inputs (c_ab, c_a, c_b, n_pcs)."""
+    keep = _Keep()
+    t = _make_table(table, keep)
+    p = _make_preds([a_terms, b_terms], [_dtype_code(c) for c in table.cols], keep)
+    s = _make_spec(seed, rate, block_rows)
+    out = gace_gate_in()
+    _check(lib().gace_probe_pcs(ctx, ctypes.byref(t), ctypes.byref(p), ctypes.byref(s), ctypes.byref(out),
+                                _stream_handle(stream)))
+    return out
+
+
+def _features(n_rows: float, row_bytes: float, terms: float) -> gace_cost_features:
+    f = gace_cost_features()
+    f.n_rows, f.row_bytes, f.terms = float(n_rows), float(row_bytes), float(terms)
+    return f
+
+
+def gace_cost_create(prior_ms: float = 0.85, window: int = 4096) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().gace_cost_create(prior_ms, window, ctypes.byref(h)))
+    return h.value
+
+
+def gace_cost_destroy(m: int):
+    _check(lib().gace_cost_destroy(m))
+
+
+def gace_cost_observe(m: int, n_rows: float, row_bytes: float, terms: float, ms: float):
+    f = _features(n_rows, row_bytes, terms)
+    _check(lib().gace_cost_observe(m, ctypes.byref(f), ms))
+
+
+def gace_cost_coef(m: int):
+    """-> (coefficients [fixed ms, ms per byte, ms per row-term], observations)"""
+    c = (ctypes.c_double * 3)()
+    n = ctypes.c_uint32()
+    _check(lib().gace_cost_coef(m, c, ctypes.byref(n)))
+    return [c[0], c[1], c[2]], int(n.value)
+
+
+def gace_cost_predict(m: int, n_rows: float, row_bytes: float, terms: float) -> float:
+    f = _features(n_rows, row_bytes, terms)
+    r = ctypes.c_double()
+    _check(lib().gace_cost_predict(m, ctypes.byref(f), ctypes.byref(r)))
+    return r.value
+
+
+def gace_cost_features_of(req) -> Tuple[float, float, float]:
+    arr, keep = make_requests([req])
+    f = gace_cost_features()
+    _check(lib().gace_cost_features_of(arr, ctypes.byref(f)))
+    return f.n_rows, f.row_bytes, f.terms
+
+
+def gace_cost_breakeven(device: int, host: int, row_bytes: float, terms: float) -> float:
+    r = ctypes.c_double()
+    _check(lib().gace_cost_breakeven(device, host, row_bytes, terms, ctypes.byref(r)))
+    return r.value
+
+
+def gace_cache_create(capacity: int = 1 << 16) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().gace_cache_create(capacity, ctypes.byref(h)))
+    return h.value
+
+
+def gace_cache_destroy(c: int):
+    _check(lib().gace_cache_destroy(c))
+
+
+def _sel_args(table: Table, preds, seed, rate, block_rows, keep):
+    t = _make_table(table, keep)
+    p = _make_preds(preds, [_dtype_code(c) for c in table.cols], keep)
+    return t, p, _make_spec(seed, rate, block_rows)
+
+
+def gace_cache_lookup(c: int, table: Table, preds, seed: int = 0, rate: float = 1.0, block_rows: int = 4096):
+    """-> (counts, hit mask, n_hit, sampled_rows, kept_blocks); counts of misses are 0."""
+    keep = _Keep()
+    t, p, s = _sel_args(table, preds, seed, rate, block_rows, keep)
+    n = max(len(preds), 1)
+    counts = np.zeros(n, dtype=np.uint64)
+    hit = np.zeros(n, dtype=np.uint8)
+    info = gace_probe_info()
+    nh = ctypes.c_uint32()
+    _check(lib().gace_cache_lookup(c, ctypes.byref(t), ctypes.byref(p), ctypes.byref(s),
+                                   counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                   hit.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(info),
+                                   ctypes.byref(nh)))
+    k = len(preds)
+    return counts[:k], hit[:k].astype(bool), int(nh.value), int(info.sampled_rows), int(info.kept_blocks)
+
+
+def gace_cache_insert(c: int, table: Table, preds, counts, sampled_rows: int, kept_blocks: int, seed: int = 0,
+                      rate: float = 1.0, block_rows: int = 4096):
+    keep = _Keep()
+    t, p, s = _sel_args(table, preds, seed, rate, block_rows, keep)
+    cs = np.zeros(max(len(preds), 1), dtype=np.uint64)
+    cs[:len(preds)] = np.asarray(counts, dtype=np.uint64)
+    info = gace_probe_info()
+    info.sampled_rows, info.kept_blocks = sampled_rows, kept_blocks
+    _check(lib().gace_cache_insert(c, ctypes.byref(t), ctypes.byref(p), ctypes.byref(s),
+                                   cs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), ctypes.byref(info)))
+
+
+def gace_cache_invalidate(c: int, table_id: int):
+    _check(lib().gace_cache_invalidate(c, table_id))
+
+
+def gace_cache_stats_get(c: int) -> dict:
+    st = gace_cache_stats()
+    _check(lib().gace_cache_stats_get(c, ctypes.byref(st)))
+    return {n: int(getattr(st, n)) for n, _ in gace_cache_stats._fields_}
+
+
+def gace_probe_selectivity_cached(ctx: int, c: int, table: Table, preds, seed: int = 0, rate: float = 1.0,
+                                  block_rows: int = 4096, stream=None):
+    """-> (counts, sampled_rows, kept_blocks, n_hit)"""
+    keep = _Keep()
+    t, p, s = _sel_args(table, preds, seed, rate, block_rows, keep)
+    counts = np.zeros(max(len(preds), 1), dtype=np.uint64)
+    info = gace_probe_info()
+    nh = ctypes.c_uint32()
+    _check(lib().gace_probe_selectivity_cached(ctx, c, ctypes.byref(t), ctypes.byref(p), ctypes.byref(s),
+                                               counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                               ctypes.byref(info), ctypes.byref(nh), _stream_handle(stream)))
+    return counts[:len(preds)], int(info.sampled_rows), int(info.kept_blocks), int(nh.value)
+
+
+def gace_join_freq_cached(ctx: int, c: int, R: Keys, S: Keys, stream=None):
+    """-> (result dict, hit)"""
+    r, s = _make_keys(R), _make_keys(S)
+    out = gace_join_result()
+    hit = ctypes.c_uint32()
+    _check(lib().gace_join_freq_cached(ctx, c, ctypes.byref(r), ctypes.byref(s), ctypes.byref(out),
+                                       ctypes.byref(hit), _stream_handle(stream)))
+    return dict(join_card=int(out.join_card), ndv_R=int(out.ndv_R), ndv_S=int(out.ndv_S),
+                n_R=int(out.n_R), n_S=int(out.n_S)), bool(hit.value)

@@ -1,7 +1,8 @@
-"""The C-ABI library loads and exports every function include/gace.h declares;
+"""The C-ABI library loads and exports every function include/*.h declares;
 the ctypes layouts match the header; host-side request validation (no GPU).
 """
 import ctypes
+import glob
 import os
 import re
 
@@ -11,7 +12,7 @@ import pytest
 import paper_2512_19750_amd as g
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gace.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 @pytest.fixture(scope="module")
@@ -23,7 +24,7 @@ def L():
 
 
 def _declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:gace_status|const char\*)\s+(gace_\w+)\s*\(", src, flags=re.M)))
 
