@@ -342,6 +342,68 @@ def serve_main(args):
 
 
 S_SERVE = 0x2512197500 + 40
+S_H2D = 0x2512197500 + 50
+
+
+def h2d_main(args):
+    """Exp. A on MI355X: a selectivity probe of a host-resident table, split
+    into sampler, gather, host-to-device copy, kernel, download and reduction,
+    for sample sizes N from 1e4 to the whole table, moving only the referenced
+    columns (key-only) or every column (full row); the same probe of the table
+    resident in HBM is timed beside it."""
+    import torch
+
+    import datagen
+    import paper_2512_19750_amd as g
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n_rows = int(args.h2d_rows)
+    t = datagen.uniform_i32_table(n_rows, 4, S_H2D, table_id=1)
+    t0 = time.time()
+    host = datagen.host_table(t, nthreads=16)
+    resident = [torch.from_numpy(c).to(dev) for c in host]
+    torch.cuda.synchronize()
+    print("[h2d] table %d rows x 4 int32 (%.2f GB) in host memory, %.1fs" % (n_rows, 16 * n_rows / 1e9,
+                                                                         time.time() - t0), file=sys.stderr,
+          flush=True)
+    pred = [[(0, g.RANGE, (100, 300)), (1, g.RANGE, (0, 500))]]     # key-only: 2 of 4 columns
+    ctx = g.gace_create(0, 8 << 30)
+    points = []
+    try:
+        for n_target in [float(x) for x in args.h2d_n.split(",")]:
+            rate = min(1.0, n_target / n_rows)
+            row = {"n_target": n_target, "rate": rate}
+            for mode in ("key_only", "full_row"):
+                runs = []
+                for rep in range(1 + args.h2d_reps):
+                    c, n, k, st = g.gace_probe_selectivity_host(ctx, host, 1, pred, S_H2D, rate, 4096,
+                                                                key_only=(mode == "key_only"))
+                    if rep:
+                        runs.append(st)
+                med = {key: sorted(r[key] for r in runs)[len(runs) // 2]
+                       for key in ("total_ms", "sample_ms", "gather_ms", "h2d_ms", "kernel_ms", "d2h_ms",
+                                   "reduce_ms")}
+                med = {key: round(v, 4) for key, v in med.items()}
+                med["h2d_bytes"] = runs[0]["h2d_bytes"]
+                med["h2d_gbps"] = round(med["h2d_bytes"] / (med["h2d_ms"] * 1e6), 2) if med["h2d_ms"] else None
+                med["chunks"] = runs[0]["chunks"]
+                row[mode] = med
+                row["sampled_rows"], row["count"] = n, int(c[0])
+            lat = []
+            for rep in range(1 + args.h2d_reps):
+                s0 = time.perf_counter()
+                c2, n2, _ = g.gace_probe_selectivity(ctx, g.Table(resident, 1), pred, S_H2D, rate, 4096)
+                if rep:
+                    lat.append((time.perf_counter() - s0) * 1e3)
+            assert int(c2[0]) == row["count"] and n2 == row["sampled_rows"]
+            row["resident_ms"] = round(sorted(lat)[len(lat) // 2], 4)
+            points.append(row)
+            print("[h2d] %s" % json.dumps(row), file=sys.stderr, flush=True)
+    finally:
+        g.gace_destroy(ctx)
+    print(json.dumps({"metric": "host-resident probe time decomposition (Exp. A), key-only vs full row",
+                      "unit": "ms", "n_gpus": 1, "table_rows": n_rows, "columns": "4 x int32, predicate on 2",
+                      "data": "synthetic (seeded counter-based generator)", "points": points}))
 
 
 def main():
@@ -365,6 +427,11 @@ def main():
     ap.add_argument("--serve-point-qps", type=float, default=1000.0,
                     help="batch benchmark: also serve its requests at this Poisson rate (0: skip)")
     ap.add_argument("--serve-point-seconds", type=float, default=5.0)
+    ap.add_argument("--h2d", action="store_true",
+                    help="run the host-resident table decomposition (Exp. A) instead of the batch benchmark")
+    ap.add_argument("--h2d-rows", type=float, default=1e8)
+    ap.add_argument("--h2d-n", default="1e4,1e5,1e6,1e7,1e8")
+    ap.add_argument("--h2d-reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the probe on a single MI355X "
@@ -373,6 +440,9 @@ def main():
 
     if args.serve:
         serve_main(args)
+        return
+    if args.h2d:
+        h2d_main(args)
         return
 
     import torch

@@ -139,6 +139,17 @@ class gace_cache_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("hits", "misses", "inserts", "evictions", "invalidated", "entries")]
 
 
+# gace_host.h
+class gace_host_opts(ctypes.Structure):
+    _fields_ = [("key_only", ctypes.c_uint32), ("gather_threads", ctypes.c_uint32), ("chunk_rows", ctypes.c_uint64)]
+
+
+class gace_transfer_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("total_ms", "sample_ms", "gather_ms", "h2d_ms", "kernel_ms",
+                                               "d2h_ms", "reduce_ms")] + \
+               [("h2d_bytes", ctypes.c_uint64), ("chunks", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 ABI_FUNCTIONS = [
     "gace_create", "gace_destroy", "gace_last_error", "gace_version", "gace_check_request",
     "gace_probe_selectivity", "gace_join_freq", "gace_batch_run", "gace_autotune", "gace_get_schedule",
@@ -152,6 +163,8 @@ ABI_FUNCTIONS = [
     "gace_cost_features_of", "gace_cost_breakeven",
     "gace_cache_create", "gace_cache_destroy", "gace_cache_lookup", "gace_cache_insert", "gace_cache_invalidate",
     "gace_cache_stats_get", "gace_probe_selectivity_cached", "gace_join_freq_cached",
+    # gace_host.h
+    "gace_probe_selectivity_host",
 ]
 
 _lib = None
@@ -228,6 +241,10 @@ def lib():
                                                ctypes.POINTER(gace_probe_info), ctypes.POINTER(u32), P], i32),
             "gace_join_freq_cached": ([P, P, ctypes.POINTER(gace_keys), ctypes.POINTER(gace_keys),
                                        ctypes.POINTER(gace_join_result), ctypes.POINTER(u32), P], i32),
+            "gace_probe_selectivity_host": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
+                                             ctypes.POINTER(gace_sample_spec), ctypes.POINTER(gace_host_opts),
+                                             ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(gace_probe_info),
+                                             ctypes.POINTER(gace_transfer_stats), P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -741,3 +758,40 @@ def gace_join_freq_cached(ctx: int, c: int, R: Keys, S: Keys, stream=None):
                                        ctypes.byref(hit), _stream_handle(stream)))
     return dict(join_card=int(out.join_card), ndv_R=int(out.ndv_R), ndv_S=int(out.ndv_S),
                 n_R=int(out.n_R), n_S=int(out.n_S)), bool(hit.value)
+
+
+# ---------------------------------------------------------------- gace_host.h
+_NP_DTYPE = {np.dtype(np.int32): I32, np.dtype(np.int64): I64, np.dtype(np.float32): F32}
+
+
+def gace_probe_selectivity_host(ctx: int, cols, table_id: int, preds, seed: int = 0, rate: float = 1.0,
+                                block_rows: int = 4096, key_only: bool = True, chunk_rows: int = 0,
+                                gather_threads: int = 0, stream=None):
+    """Probe a table held in host memory (cols: C-contiguous numpy arrays of
+    equal length).  -> (counts, sampled_rows, kept_blocks, transfer stats dict)"""
+    keep = _Keep()
+    arr = keep.add((gace_column * max(len(cols), 1))())
+    dts = []
+    for i, c in enumerate(cols):
+        if not c.flags["C_CONTIGUOUS"] or c.dtype not in _NP_DTYPE:
+            raise TypeError("host columns must be C-contiguous int32, int64 or float32 arrays")
+        arr[i].data = c.ctypes.data
+        arr[i].dtype = _NP_DTYPE[c.dtype]
+        dts.append(_NP_DTYPE[c.dtype])
+    t = gace_table()
+    t.n_rows = int(cols[0].shape[0]) if cols else 0
+    t.cols = ctypes.cast(arr, ctypes.POINTER(gace_column))
+    t.n_cols = len(cols)
+    t.table_id = table_id
+    p = _make_preds(preds, dts, keep)
+    s = _make_spec(seed, rate, block_rows)
+    o = gace_host_opts()
+    o.key_only, o.chunk_rows, o.gather_threads = (1 if key_only else 0), chunk_rows, gather_threads
+    counts = np.zeros(max(len(preds), 1), dtype=np.uint64)
+    info = gace_probe_info()
+    st = gace_transfer_stats()
+    _check(lib().gace_probe_selectivity_host(ctx, ctypes.byref(t), ctypes.byref(p), ctypes.byref(s), ctypes.byref(o),
+                                             counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                             ctypes.byref(info), ctypes.byref(st), _stream_handle(stream)))
+    stats = {n: getattr(st, n) for n, _ in gace_transfer_stats._fields_ if n != "reserved"}
+    return counts[:len(preds)], int(info.sampled_rows), int(info.kept_blocks), stats

@@ -1652,9 +1652,34 @@ __global__ void __launch_bounds__(kWG) gace_init_kernel(const uint8_t* plan, uin
     }
 }
 
+// Kept-block bit mask for a host-resident table: bit (b mod 32) of word b / 32
+// is set iff block b is kept (the same decision as decide_blocks).  One
+// thread per 32-bit word, so every word is written whole with one store.
+__global__ void __launch_bounds__(kWG) gace_sample_mask_kernel(uint64_t n_blocks, uint64_t seed, uint32_t table_id,
+                                                               uint64_t thr, uint32_t* mask) {
+    const uint64_t w = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    if (w >= (n_blocks + 31) / 32) return;
+    uint32_t bits = 0;
+    for (uint32_t j = 0; j < 32; ++j) {
+        const uint64_t b = w * 32 + j;
+        if (b < n_blocks && (uint64_t)block_word0(b, table_id, seed) < thr) bits |= 1u << j;
+    }
+    mask[w] = bits;
+}
+
 }  // namespace gace
 
 extern "C" {
+
+hipError_t gace_launch_sample_mask(uint64_t n_blocks, uint64_t seed, uint32_t table_id, uint64_t thr, void* mask,
+                                   hipStream_t stream) {
+    const uint64_t words = (n_blocks + 31) / 32;
+    const uint64_t grid = (words + gace::kWG - 1) / gace::kWG;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(gace::gace_sample_mask_kernel, dim3((uint32_t)grid), dim3(gace::kWG), 0, stream, n_blocks,
+                       seed, table_id, thr, (uint32_t*)mask);
+    return hipGetLastError();
+}
 
 // launchers used by the host runtime (internal; not part of the public ABI)
 hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,

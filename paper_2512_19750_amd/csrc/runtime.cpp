@@ -413,6 +413,10 @@ gace_status gace_destroy(gace_ctx* c) {
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     for (hipEvent_t e : {c->ev_s0, c->ev_s1, c->ev_j0, c->ev_j1})
         if (e) (void)hipEventDestroy(e);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    for (hipEvent_t e : {c->ev_h0[0], c->ev_h0[1], c->ev_h1[0], c->ev_h1[1], c->ev_d2h})
+        if (e) (void)hipEventDestroy(e);
+    if (c->h_hp) (void)hipHostFree(c->h_hp);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_result) (void)hipHostFree(c->h_result);
     if (c->ws) (void)hipFree(c->ws);

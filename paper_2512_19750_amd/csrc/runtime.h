@@ -64,6 +64,11 @@ struct gace_ctx {
     double last_scan_ms = 0.0, last_join_ms = 0.0;
     uint64_t last_scan_bytes = 0, last_join_bytes = 0;
     std::map<std::string, gace_schedule> tuned;   // shape bucket -> schedule
+    // host-resident tables: copy stream, per-slot copy events, pinned staging
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_h0[2] = {nullptr, nullptr}, ev_h1[2] = {nullptr, nullptr}, ev_d2h = nullptr;
+    uint8_t* h_hp = nullptr;
+    uint64_t h_hp_bytes = 0;
     bool trace = false;                           // record per-item device timestamps
     std::vector<TraceRec> last_trace;
     double ticks_per_us = 0.0;
