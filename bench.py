@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -406,6 +408,83 @@ def h2d_main(args):
                       "data": "synthetic (seeded counter-based generator)", "points": points}))
 
 
+S_EST = 0x2512197500 + 60
+
+
+def est_main(args):
+    """Exp. B on MI355X: spread of the sampled estimates of sel(A AND B) and of
+    PCS across sampling seeds (Est.CV) against the probing budget, for block
+    sampling (4096-row blocks) and row sampling, on the table as generated
+    and on the same table clustered by A's column.  Each (layout, block size,
+    budget) point is one batched launch of `seeds` probes."""
+    import torch
+
+    import datagen
+    import paper_2512_19750_amd as g
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n_rows = int(args.est_rows)
+    t = datagen.config2_table(n_rows)
+    c0 = datagen.device_column(t.cols[0], n_rows, dev)
+    c1 = datagen.device_column(t.cols[1], n_rows, dev)       # c0 + U{-50..50}: correlated with c0
+    order = torch.argsort(c0, stable=True)
+    layouts = {"random": [c0, c1], "clustered": [c0[order].contiguous(), c1[order].contiguous()]}
+    del order
+    torch.cuda.synchronize()
+    A = [(0, g.RANGE, (1000, 1100))]
+    B = [(1, g.RANGE, (1000, 1100))]
+    preds = [A, B, A + B]
+    ctx = g.gace_create(0, 8 << 30)
+    g.gace_set_graph(ctx, True)
+    points = []
+    try:
+        truth = g.gace_probe_selectivity(ctx, g.Table(layouts["random"], 2), preds, 0, 1.0, 4096)
+        ca, cb, cab = (int(x) for x in truth[0])
+        sel_true = cab / n_rows
+        pcs_true = cab * n_rows / (ca * cb)
+        print("[est] truth: c_a %d c_b %d c_ab %d of %d rows: sel %.3e PCS %.3f" % (ca, cb, cab, n_rows, sel_true,
+                                                                                  pcs_true), file=sys.stderr,
+              flush=True)
+        for layout, cols in layouts.items():
+            tab = g.Table(cols, 2)
+            for brows in (4096, 1):
+                for rate in [float(x) for x in args.est_rates.split(",")]:
+                    reqs = [g.SelRequest(tab, preds, S_EST + k, rate, brows) for k in range(args.est_seeds)]
+                    arr = g.make_requests(reqs)
+                    g.gace_batch_run(ctx, reqs, prepared=arr)              # warm
+                    t0 = time.perf_counter()
+                    g.gace_batch_run(ctx, reqs, prepared=arr)
+                    ms = (time.perf_counter() - t0) * 1e3
+                    sel, pcs, rows = [], [], []
+                    for q in reqs:
+                        c, n, _ = q.result()
+                        a_, b_, ab_ = (int(x) for x in c)
+                        rows.append(n)
+                        if n:
+                            sel.append(ab_ / n)
+                        if a_ and b_:
+                            pcs.append(ab_ * n / (a_ * b_))
+                    def cv(x):
+                        m = float(np.mean(x)) if x else math.nan
+                        return (float(np.std(x, ddof=1)) / m) if len(x) > 1 and m else math.nan, m
+                    cv_sel, m_sel = cv(sel)
+                    cv_pcs, m_pcs = cv(pcs)
+                    row = {"layout": layout, "block_rows": brows, "rate": rate, "seeds": args.est_seeds,
+                           "mean_sampled_rows": round(float(np.mean(rows)), 1),
+                           "sel_cv": round(cv_sel, 4), "sel_bias": round(m_sel / sel_true - 1, 4),
+                           "pcs_cv": round(cv_pcs, 4) if not math.isnan(cv_pcs) else None,
+                           "pcs_bias": round(m_pcs / pcs_true - 1, 4) if pcs else None,
+                           "pcs_defined": len(pcs), "batch_ms": round(ms, 3)}
+                    points.append(row)
+                    print("[est] %s" % json.dumps(row), file=sys.stderr, flush=True)
+    finally:
+        g.gace_destroy(ctx)
+    print(json.dumps({"metric": "Est.CV of sel(A and B) and PCS across sampling seeds vs budget (Exp. B)",
+                      "n_gpus": 1, "table_rows": n_rows, "data": "synthetic: c0 Zipf(1.1) over [0, 1e6), "
+                      "c1 = c0 + U{-50..50}; A = c0 in [1000, 1100), B = c1 in [1000, 1100)",
+                      "truth": {"sel": sel_true, "pcs": pcs_true}, "points": points}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,6 +511,11 @@ def main():
     ap.add_argument("--h2d-rows", type=float, default=1e8)
     ap.add_argument("--h2d-n", default="1e4,1e5,1e6,1e7,1e8")
     ap.add_argument("--h2d-reps", type=int, default=3)
+    ap.add_argument("--est", action="store_true",
+                    help="run the estimate-stability sweep (Exp. B) instead of the batch benchmark")
+    ap.add_argument("--est-rows", type=float, default=1e8)
+    ap.add_argument("--est-rates", default="0.0005,0.002,0.01,0.05")
+    ap.add_argument("--est-seeds", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the probe on a single MI355X "
@@ -443,6 +527,9 @@ def main():
         return
     if args.h2d:
         h2d_main(args)
+        return
+    if args.est:
+        est_main(args)
         return
 
     import torch

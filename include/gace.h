@@ -148,6 +148,9 @@ typedef struct {
     uint64_t ndv_S;
     uint64_t n_R;       /* sampled keys of R */
     uint64_t n_S;
+    uint64_t f1_R, f1_S; /* distinct sampled keys seen exactly once (the f_1 of
+                            NDV scale-up estimators such as GEE) */
+    uint64_t f2_R, f2_S; /* ... exactly twice */
 } gace_join_result;
 
 /* A request for gace_batch_run / gace_server_submit.  kind selects which

@@ -136,7 +136,7 @@ def join_freq(keys_r: np.ndarray, tid_r: int, seed_r: int, rate_r: float, br: in
               keys_s: np.ndarray, tid_s: int, seed_s: int, rate_s: float, bs: int) -> Dict[str, int]:
     keys_r = np.ascontiguousarray(keys_r, dtype=np.int64)
     keys_s = np.ascontiguousarray(keys_s, dtype=np.int64)
-    out = np.zeros(5, dtype=np.uint64)
+    out = np.zeros(9, dtype=np.uint64)
     rc = lib().orc_join_freq(keys_r.ctypes.data, keys_r.shape[0], tid_r, seed_r, float(rate_r), br,
                              keys_s.ctypes.data, keys_s.shape[0], tid_s, seed_s, float(rate_s), bs,
                              out.ctypes.data)
@@ -144,7 +144,8 @@ def join_freq(keys_r: np.ndarray, tid_r: int, seed_r: int, rate_r: float, br: in
         raise OverflowError("n_R * n_S >= 2^64")
     if rc != 0:
         raise ValueError("orc_join_freq rejected its arguments (%d)" % rc)
-    return dict(join_card=int(out[0]), ndv_R=int(out[1]), ndv_S=int(out[2]), n_R=int(out[3]), n_S=int(out[4]))
+    return dict(join_card=int(out[0]), ndv_R=int(out[1]), ndv_S=int(out[2]), n_R=int(out[3]), n_S=int(out[4]),
+                f1_R=int(out[5]), f1_S=int(out[6]), f2_R=int(out[7]), f2_S=int(out[8]))
 
 
 def sort_i64(keys: np.ndarray) -> np.ndarray:

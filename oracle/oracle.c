@@ -258,7 +258,7 @@ static int64_t* sample_keys(const int64_t* keys, uint64_t n, uint32_t tid, uint6
 int orc_join_freq(const int64_t* keys_r, uint64_t n_r, uint32_t tid_r, uint64_t seed_r, double rate_r,
                   uint32_t block_rows_r,
                   const int64_t* keys_s, uint64_t n_s, uint32_t tid_s, uint64_t seed_s, double rate_s,
-                  uint32_t block_rows_s, uint64_t out[5]) {
+                  uint32_t block_rows_s, uint64_t out[9]) {
     if (!valid_block_rows(block_rows_r) || !valid_block_rows(block_rows_s)) return -1;
     if (!valid_rate(rate_r) || !valid_rate(rate_s)) return -1;
     if ((n_r && !keys_r) || (n_s && !keys_s) || !out) return -1;
@@ -273,6 +273,7 @@ int orc_join_freq(const int64_t* keys_r, uint64_t n_r, uint32_t tid_r, uint64_t 
     /* runs of equal keys in the sorted samples are the frequencies f(k);
        walk both run lists in key order */
     uint64_t ndv_r = 0, ndv_s = 0, join = 0, i = 0, j = 0;
+    uint64_t f1_r = 0, f1_s = 0, f2_r = 0, f2_s = 0;   /* keys seen exactly once / twice */
     while (i < mr || j < ms) {
         int take_r, take_s;
         if (i < mr && j < ms) { take_r = r[i] <= s[j]; take_s = s[j] <= r[i]; }
@@ -282,8 +283,11 @@ int orc_join_freq(const int64_t* keys_r, uint64_t n_r, uint32_t tid_r, uint64_t 
         if (take_r) { while (i < mr && r[i] == k) { ++fr; ++i; } ndv_r += 1; }
         if (take_s) { while (j < ms && s[j] == k) { ++fs; ++j; } ndv_s += 1; }
         join += fr * fs;
+        f1_r += fr == 1; f2_r += fr == 2;
+        f1_s += fs == 1; f2_s += fs == 2;
     }
     out[0] = join; out[1] = ndv_r; out[2] = ndv_s; out[3] = mr; out[4] = ms;
+    out[5] = f1_r; out[6] = f1_s; out[7] = f2_r; out[8] = f2_s;
     free(r); free(s);
     return 0;
 }

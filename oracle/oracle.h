@@ -54,11 +54,13 @@ int orc_probe_selectivity(uint64_t n_rows, const orc_col* cols, uint32_t n_cols,
                           uint64_t* counts, uint64_t* sampled_rows, uint64_t* kept_blocks,
                           int nthreads);
 
-/* out = {join, ndv_R, ndv_S, n_R, n_S}; 0, -1 (invalid) or -3 (overflow). */
+/* out = {join, ndv_R, ndv_S, n_R, n_S, f1_R, f1_S, f2_R, f2_S}, where f1 / f2
+   count the distinct sampled keys seen exactly once / twice on that side;
+   0, -1 (invalid) or -3 (overflow). */
 int orc_join_freq(const int64_t* keys_r, uint64_t n_r, uint32_t tid_r, uint64_t seed_r, double rate_r,
                   uint32_t block_rows_r,
                   const int64_t* keys_s, uint64_t n_s, uint32_t tid_s, uint64_t seed_s, double rate_s,
-                  uint32_t block_rows_s, uint64_t out[5]);
+                  uint32_t block_rows_s, uint64_t out[9]);
 
 /* sorts int64 keys ascending in place (step of orc_join_freq, exported for tests) */
 int orc_sort_i64(int64_t* keys, uint64_t n);

@@ -66,9 +66,15 @@ class gace_keys(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("spec", gace_sample_spec)]
 
 
+JOIN_FIELDS = ("join_card", "ndv_R", "ndv_S", "n_R", "n_S", "f1_R", "f1_S", "f2_R", "f2_S")
+
+
 class gace_join_result(ctypes.Structure):
-    _fields_ = [("join_card", ctypes.c_uint64), ("ndv_R", ctypes.c_uint64), ("ndv_S", ctypes.c_uint64),
-                ("n_R", ctypes.c_uint64), ("n_S", ctypes.c_uint64)]
+    _fields_ = [(n, ctypes.c_uint64) for n in JOIN_FIELDS]
+
+
+def _join_dict(o) -> dict:
+    return {n: int(getattr(o, n)) for n in JOIN_FIELDS}
 
 
 class gace_request(ctypes.Structure):
@@ -150,6 +156,15 @@ class gace_transfer_stats(ctypes.Structure):
                [("h2d_bytes", ctypes.c_uint64), ("chunks", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+# gace_est.h
+class gace_sel_estimate(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("p", "sel", "card", "card_ht")]
+
+
+class gace_join_estimate(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("p_R", "p_S", "join_ht", "ndv_R", "ndv_S")]
+
+
 ABI_FUNCTIONS = [
     "gace_create", "gace_destroy", "gace_last_error", "gace_version", "gace_check_request",
     "gace_probe_selectivity", "gace_join_freq", "gace_batch_run", "gace_autotune", "gace_get_schedule",
@@ -165,6 +180,8 @@ ABI_FUNCTIONS = [
     "gace_cache_stats_get", "gace_probe_selectivity_cached", "gace_join_freq_cached",
     # gace_host.h
     "gace_probe_selectivity_host",
+    # gace_est.h
+    "gace_estimate_selectivity", "gace_estimate_join",
 ]
 
 _lib = None
@@ -241,6 +258,10 @@ def lib():
                                                ctypes.POINTER(gace_probe_info), ctypes.POINTER(u32), P], i32),
             "gace_join_freq_cached": ([P, P, ctypes.POINTER(gace_keys), ctypes.POINTER(gace_keys),
                                        ctypes.POINTER(gace_join_result), ctypes.POINTER(u32), P], i32),
+            "gace_estimate_selectivity": ([u64, ctypes.POINTER(gace_probe_info), u64, ctypes.POINTER(gace_sample_spec),
+                                           ctypes.POINTER(gace_sel_estimate)], i32),
+            "gace_estimate_join": ([ctypes.POINTER(gace_join_result), u64, ctypes.POINTER(gace_sample_spec), u64,
+                                    ctypes.POINTER(gace_sample_spec), ctypes.POINTER(gace_join_estimate)], i32),
             "gace_probe_selectivity_host": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
                                              ctypes.POINTER(gace_sample_spec), ctypes.POINTER(gace_host_opts),
                                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(gace_probe_info),
@@ -403,9 +424,7 @@ class JoinRequest:
         r.join = ctypes.pointer(self.out)
 
     def result(self):
-        o = self.out
-        return dict(join_card=int(o.join_card), ndv_R=int(o.ndv_R), ndv_S=int(o.ndv_S),
-                    n_R=int(o.n_R), n_S=int(o.n_S))
+        return _join_dict(self.out)
 
 
 def make_requests(reqs) -> Tuple[ctypes.Array, _Keep]:
@@ -455,8 +474,7 @@ def gace_join_freq(ctx: int, R: Keys, S: Keys, stream=None) -> dict:
     r, s = _make_keys(R), _make_keys(S)
     out = gace_join_result()
     _check(lib().gace_join_freq(ctx, ctypes.byref(r), ctypes.byref(s), ctypes.byref(out), _stream_handle(stream)))
-    return dict(join_card=int(out.join_card), ndv_R=int(out.ndv_R), ndv_S=int(out.ndv_S),
-                n_R=int(out.n_R), n_S=int(out.n_S))
+    return _join_dict(out)
 
 
 def gace_batch_run(ctx: int, reqs, stream=None, raise_on_error: bool = True, prepared=None) -> List[int]:
@@ -756,8 +774,7 @@ def gace_join_freq_cached(ctx: int, c: int, R: Keys, S: Keys, stream=None):
     hit = ctypes.c_uint32()
     _check(lib().gace_join_freq_cached(ctx, c, ctypes.byref(r), ctypes.byref(s), ctypes.byref(out),
                                        ctypes.byref(hit), _stream_handle(stream)))
-    return dict(join_card=int(out.join_card), ndv_R=int(out.ndv_R), ndv_S=int(out.ndv_S),
-                n_R=int(out.n_R), n_S=int(out.n_S)), bool(hit.value)
+    return _join_dict(out), bool(hit.value)
 
 
 # ---------------------------------------------------------------- gace_host.h
@@ -795,3 +812,26 @@ def gace_probe_selectivity_host(ctx: int, cols, table_id: int, preds, seed: int 
                                              ctypes.byref(info), ctypes.byref(st), _stream_handle(stream)))
     stats = {n: getattr(st, n) for n, _ in gace_transfer_stats._fields_ if n != "reserved"}
     return counts[:len(preds)], int(info.sampled_rows), int(info.kept_blocks), stats
+
+
+# ---------------------------------------------------------------- gace_est.h
+def gace_estimate_selectivity(count: int, sampled_rows: int, kept_blocks: int, n_rows: int, rate: float = 1.0,
+                              block_rows: int = 4096, seed: int = 0) -> dict:
+    info = gace_probe_info()
+    info.sampled_rows, info.kept_blocks = sampled_rows, kept_blocks
+    sp = _make_spec(seed, rate, block_rows)
+    e = gace_sel_estimate()
+    _check(lib().gace_estimate_selectivity(count, ctypes.byref(info), n_rows, ctypes.byref(sp), ctypes.byref(e)))
+    return {n: getattr(e, n) for n, _ in gace_sel_estimate._fields_}
+
+
+def gace_estimate_join(res: dict, n_rows_R: int, rate_R: float, n_rows_S: int, rate_S: float,
+                       block_rows_R: int = 4096, block_rows_S: int = 4096) -> dict:
+    r = gace_join_result()
+    for n in JOIN_FIELDS:
+        setattr(r, n, int(res[n]))
+    sr, ss = _make_spec(0, rate_R, block_rows_R), _make_spec(0, rate_S, block_rows_S)
+    e = gace_join_estimate()
+    _check(lib().gace_estimate_join(ctypes.byref(r), n_rows_R, ctypes.byref(sr), n_rows_S, ctypes.byref(ss),
+                                    ctypes.byref(e)))
+    return {n: getattr(e, n) for n, _ in gace_join_estimate._fields_}

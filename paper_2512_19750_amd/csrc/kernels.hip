@@ -1333,7 +1333,7 @@ __device__ __forceinline__ void agg_clear(AggLds& T, uint32_t slots) {
 template <typename Pass>
 __device__ void aggregate(AggLds& T, Pass&& pass, uint32_t* s_ctl, uint32_t* stack,
                           GACE_GLOBAL MergeEntry* emit, unsigned long long& n0, unsigned long long& n1,
-                          unsigned long long& jn, JoinAcc& acc, uint32_t& passes) {
+                          unsigned long long& jn, uint32_t (&ff)[4], JoinAcc& acc, uint32_t& passes) {
     const int lane = threadIdx.x & 63;
     if (threadIdx.x == 0) {
         stack[0] = 1;
@@ -1404,6 +1404,10 @@ __device__ void aggregate(AggLds& T, Pass&& pass, uint32_t* s_ctl, uint32_t* sta
                     n0 += x != 0;
                     n1 += y != 0;
                     jn += (unsigned long long)x * y;
+                    ff[0] += x == 1;      // keys seen once / twice per side
+                    ff[1] += y == 1;
+                    ff[2] += x == 2;
+                    ff[3] += y == 2;
                 }
             }
         }
@@ -1430,6 +1434,7 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
     GACE_GLOBAL uint32_t* chunk_cnt = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->chunk_off);
     uint32_t* done = (uint32_t*)(a.arena_base + jd->done_off);
     unsigned long long jn = 0, n0 = 0, n1 = 0;
+    uint32_t ff[4] = {0, 0, 0, 0};
     const bool dead = __hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     const GACE_GLOBAL int64_t* bufR = (const GACE_GLOBAL int64_t*)(a.arena_base + acc.buf_off);
     const GACE_GLOBAL int64_t* bufS = bufR + acc.nkeys[0];
@@ -1468,7 +1473,7 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
                     for (uint32_t c = 0; c < U.b; ++c)
                         agg_entries(T, merge + (uint64_t)(U.a + c) * kChunkKeys, chunk_cnt[U.a + c], m, res, s_ctl);
                 },
-                s_ctl, stack, nullptr, n0, n1, jn, acc, passes);
+                s_ctl, stack, nullptr, n0, n1, jn, ff, acc, passes);
             ++n_taken;
             if (threadIdx.x == 0) s_ctl[2] = claim_next;
             __syncthreads();
@@ -1487,14 +1492,14 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
         };
         agg_size(T, hi - lo, a.agg_slots);
         if (U.kind == AU_CHUNK) {
-            aggregate(T, pass, s_ctl, stack, merge + (uint64_t)U.b * kChunkKeys, n0, n1, jn, acc, passes);
+            aggregate(T, pass, s_ctl, stack, merge + (uint64_t)U.b * kChunkKeys, n0, n1, jn, ff, acc, passes);
             if (threadIdx.x == 0) {
                 chunk_cnt[U.b] = s_ctl[6];
                 __threadfence();
                 atomicAdd(&done[U.ord], 1u);
             }
         } else {
-            aggregate(T, pass, s_ctl, stack, nullptr, n0, n1, jn, acc, passes);
+            aggregate(T, pass, s_ctl, stack, nullptr, n0, n1, jn, ff, acc, passes);
         }
         ++n_taken;
         if (threadIdx.x == 0) s_ctl[2] = claim_next;
@@ -1504,10 +1509,17 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
     jn = block_sum(jn, s_red);
     n0 = block_sum(n0, s_red);
     n1 = block_sum(n1, s_red);
+    unsigned long long fs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fs[k] = block_sum((unsigned long long)ff[k], s_red);
     if (threadIdx.x == 0) {
         if (jn) atomicAdd(&acc.join, jn);
         if (n0) atomicAdd(&acc.ndv[0], n0);
         if (n1) atomicAdd(&acc.ndv[1], n1);
+        if (fs[0]) atomicAdd(&acc.f1[0], fs[0]);
+        if (fs[1]) atomicAdd(&acc.f1[1], fs[1]);
+        if (fs[2]) atomicAdd(&acc.f2[0], fs[2]);
+        if (fs[3]) atomicAdd(&acc.f2[1], fs[3]);
         __threadfence();
         if (atomicAdd(&acc.agg_done, 1u) == jd->n_agg - 1) {
             // last worker: the sentinel key, counted outside the tables
@@ -1516,6 +1528,10 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
             if (s0 && s1) atomicAdd(&acc.join, s0 * s1);
             if (s0) atomicAdd(&acc.ndv[0], 1ull);
             if (s1) atomicAdd(&acc.ndv[1], 1ull);
+            if (s0 == 1) atomicAdd(&acc.f1[0], 1ull);
+            if (s1 == 1) atomicAdd(&acc.f1[1], 1ull);
+            if (s0 == 2) atomicAdd(&acc.f2[0], 1ull);
+            if (s1 == 2) atomicAdd(&acc.f2[1], 1ull);
         }
     }
 }

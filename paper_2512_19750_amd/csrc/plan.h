@@ -146,6 +146,7 @@ struct MergeEntry {
 // per-join device accumulators and phase counters (zeroed before each batch)
 struct JoinAcc {
     unsigned long long join, ndv[2], n[2], sent[2];
+    unsigned long long f1[2], f2[2];        // distinct keys seen exactly once / twice per side
     unsigned long long buf_off;             // arena offset of the partitioned keys (R then S)
     unsigned long long nkeys[2];            // sampled keys per side other than the sentinel value
     unsigned long long status;              // 0 ok, 2 arena exhausted, 3 aggregation stack overflow

@@ -250,6 +250,10 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
             r.join->ndv_S = A.ndv[1];
             r.join->n_R = A.n[0];
             r.join->n_S = A.n[1];
+            r.join->f1_R = A.f1[0];
+            r.join->f1_S = A.f1[1];
+            r.join->f2_R = A.f2[0];
+            r.join->f2_S = A.f2[1];
             jalg += 8ull * (A.n[0] + A.n[1]) + 16ull * (A.ndv[0] + A.ndv[1]);
         }
         if (per_req) per_req[jo.req] = s;

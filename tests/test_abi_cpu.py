@@ -43,7 +43,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(g.gace_table) == 24
     assert ctypes.sizeof(g.gace_sample_spec) == 24
     assert ctypes.sizeof(g.gace_keys) == 48
-    assert ctypes.sizeof(g.gace_join_result) == 40
+    assert ctypes.sizeof(g.gace_join_result) == 72
     assert ctypes.sizeof(g.gace_schedule) == 32
     assert [f for f, _ in g.gace_schedule._fields_][-2] == "agg_wgs_per_cu"
     assert ctypes.sizeof(g.gace_kernel_stats) == 40

@@ -286,6 +286,10 @@ def test_join_brute_force_pairs(seed):
     assert out["join_card"] == pairs
     assert out["ndv_R"] == np.unique(r).size and out["ndv_S"] == np.unique(s).size
     assert out["n_R"] == r.size and out["n_S"] == s.size
+    # frequency of frequencies: keys seen exactly once / twice, counted by numpy
+    for side, x in (("R", r), ("S", s)):
+        _, f = np.unique(x, return_counts=True)
+        assert out["f1_" + side] == int((f == 1).sum()) and out["f2_" + side] == int((f == 2).sum())
 
 
 def test_join_sampled_vs_numpy():
@@ -314,7 +318,10 @@ def test_join_special_cases():
                          np.arange(50, 90, dtype=np.int64), 2, 0, 1.0, 64)
     assert o["join_card"] == 0
     o = oracle.join_freq(np.zeros(0, dtype=np.int64), 1, 0, 1.0, 64, eq, 2, 0, 1.0, 64)
-    assert o == dict(join_card=0, ndv_R=0, ndv_S=1, n_R=0, n_S=777)
+    assert o == dict(join_card=0, ndv_R=0, ndv_S=1, n_R=0, n_S=777, f1_R=0, f1_S=0, f2_R=0, f2_S=0)
+    o = oracle.join_freq(np.array([5, 5, 7, 9, 9, 9], dtype=np.int64), 1, 0, 1.0, 64,
+                         np.array([1, 2, 2], dtype=np.int64), 2, 0, 1.0, 64)
+    assert (o["f1_R"], o["f2_R"], o["f1_S"], o["f2_S"]) == (1, 1, 1, 1)
 
 
 def test_join_invariants():
@@ -337,7 +344,7 @@ def test_join_overflow_guard():
     # n_R * n_S >= 2^64 cannot be formed with real arrays here; the guard is
     # exercised through the C entry point with a fake length and no data read
     L = oracle.lib()
-    out = np.zeros(5, dtype=np.uint64)
+    out = np.zeros(9, dtype=np.uint64)
     rc = L.orc_join_freq(big.ctypes.data, 2**33, 1, 0, 1.0, 64, big.ctypes.data, 2**31, 2, 0, 1.0, 64,
                          out.ctypes.data)
     assert rc == -3
