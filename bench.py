@@ -409,6 +409,69 @@ def h2d_main(args):
 
 
 S_EST = 0x2512197500 + 60
+S_ZONE = 0x2512197500 + 70
+
+
+def zone_main(args):
+    """Zone maps on MI355X: build time of the per-zone min / max of a table,
+    and selectivity probes with and without zone pruning on the table as
+    generated and clustered by the filtered column."""
+    import torch
+
+    import datagen
+    import paper_2512_19750_amd as g
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n_rows = int(args.zone_rows)
+    t = datagen.uniform_i32_table(n_rows, 4, S_ZONE, table_id=7, lo=0, hi=1_000_000)
+    cols = datagen.device_table(t, dev)
+    order = torch.argsort(cols[0], stable=True)
+    layouts = {"random": cols, "clustered": [c[order].contiguous() for c in cols]}
+    del order
+    torch.cuda.synchronize()
+    preds = {"1% range on c0": [[(0, g.RANGE, (500_000, 510_000))]],
+             "1% range on c0 and c1 < 50%": [[(0, g.RANGE, (500_000, 510_000)), (1, g.RANGE, (0, 500_000))]],
+             "16 point lookups on c0": [[(0, g.EQ, (v,))] for v in range(1000, 1_000_000, 62_437)]}
+    ctx = g.gace_create(0, 8 << 30)
+    out = {"metric": "zone-map build and pruned probe time", "n_gpus": 1, "table_rows": n_rows,
+           "columns": "4 x int32 U[0, 1e6)", "build": {}, "points": []}
+
+    def timed(f, reps=5):
+        f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            s0 = time.perf_counter()
+            r = f()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - s0) * 1e3)
+        return sorted(ts)[len(ts) // 2], r
+
+    try:
+        for layout, tcols in layouts.items():
+            tab = g.Table(tcols, 7)
+            ms, zm = timed(lambda: g.gace_zonemap_build(ctx, tab), reps=1)
+            g.gace_zonemap_destroy(zm)
+            ms, zm = timed(lambda: g.gace_zonemap_build(ctx, tab), reps=1)
+            out["build"][layout] = {"ms": round(ms, 4), "gbps": round(16 * n_rows / (ms * 1e6), 1)}
+            try:
+                for name, ps in preds.items():
+                    for rate in (1.0, 0.01):
+                        m0, r0 = timed(lambda: g.gace_probe_selectivity(ctx, tab, ps, S_ZONE, rate, 4096))
+                        m1, r1 = timed(lambda: g.gace_probe_selectivity_zm(ctx, tab, zm, ps, S_ZONE, rate, 4096))
+                        assert r0[0].tolist() == r1[0].tolist() and r0[1:] == r1[1:3]
+                        row = {"layout": layout, "predicates": name, "rate": rate, "plain_ms": round(m0, 4),
+                               "zone_ms": round(m1, 4), "zones_skipped": r1[3],
+                               "zones": g.gace_zonemap_info(zm), "speedup": round(m0 / m1, 2)}
+                        out["points"].append(row)
+                        print("[zone] %s" % json.dumps(row), file=sys.stderr, flush=True)
+            finally:
+                g.gace_zonemap_destroy(zm)
+    finally:
+        g.gace_destroy(ctx)
+    print(json.dumps(out))
+
+
 
 
 def est_main(args):
@@ -516,6 +579,9 @@ def main():
     ap.add_argument("--est-rows", type=float, default=1e8)
     ap.add_argument("--est-rates", default="0.0005,0.002,0.01,0.05")
     ap.add_argument("--est-seeds", type=int, default=64)
+    ap.add_argument("--zone", action="store_true",
+                    help="run the zone-map build and pruned-probe measurement instead of the batch benchmark")
+    ap.add_argument("--zone-rows", type=float, default=4e8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the probe on a single MI355X "
@@ -530,6 +596,9 @@ def main():
         return
     if args.est:
         est_main(args)
+        return
+    if args.zone:
+        zone_main(args)
         return
 
     import torch

@@ -182,6 +182,9 @@ ABI_FUNCTIONS = [
     "gace_probe_selectivity_host",
     # gace_est.h
     "gace_estimate_selectivity", "gace_estimate_join",
+    # gace_zone.h
+    "gace_zonemap_build", "gace_zonemap_destroy", "gace_zonemap_info", "gace_zonemap_read",
+    "gace_probe_selectivity_zm",
 ]
 
 _lib = None
@@ -258,6 +261,13 @@ def lib():
                                                ctypes.POINTER(gace_probe_info), ctypes.POINTER(u32), P], i32),
             "gace_join_freq_cached": ([P, P, ctypes.POINTER(gace_keys), ctypes.POINTER(gace_keys),
                                        ctypes.POINTER(gace_join_result), ctypes.POINTER(u32), P], i32),
+            "gace_zonemap_build": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(P), P], i32),
+            "gace_zonemap_destroy": ([P], i32),
+            "gace_zonemap_info": ([P, ctypes.POINTER(u64)], i32),
+            "gace_zonemap_read": ([P, u32, P, P], i32),
+            "gace_probe_selectivity_zm": ([P, ctypes.POINTER(gace_table), P, ctypes.POINTER(gace_predicates),
+                                           ctypes.POINTER(gace_sample_spec), ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(gace_probe_info), ctypes.POINTER(u64), P], i32),
             "gace_estimate_selectivity": ([u64, ctypes.POINTER(gace_probe_info), u64, ctypes.POINTER(gace_sample_spec),
                                            ctypes.POINTER(gace_sel_estimate)], i32),
             "gace_estimate_join": ([ctypes.POINTER(gace_join_result), u64, ctypes.POINTER(gace_sample_spec), u64,
@@ -835,3 +845,48 @@ def gace_estimate_join(res: dict, n_rows_R: int, rate_R: float, n_rows_S: int, r
     _check(lib().gace_estimate_join(ctypes.byref(r), n_rows_R, ctypes.byref(sr), n_rows_S, ctypes.byref(ss),
                                     ctypes.byref(e)))
     return {n: getattr(e, n) for n, _ in gace_join_estimate._fields_}
+
+
+# ---------------------------------------------------------------- gace_zone.h
+ZONE_ROWS = 4096
+
+
+def gace_zonemap_build(ctx: int, table: Table, stream=None) -> int:
+    keep = _Keep()
+    t = _make_table(table, keep)
+    h = ctypes.c_void_p()
+    _check(lib().gace_zonemap_build(ctx, ctypes.byref(t), ctypes.byref(h), _stream_handle(stream)))
+    return h.value
+
+
+def gace_zonemap_destroy(zm: int):
+    _check(lib().gace_zonemap_destroy(zm))
+
+
+def gace_zonemap_info(zm: int) -> int:
+    n = ctypes.c_uint64()
+    _check(lib().gace_zonemap_info(zm, ctypes.byref(n)))
+    return int(n.value)
+
+
+def gace_zonemap_read(zm: int, col: int, dtype) -> Tuple[np.ndarray, np.ndarray]:
+    """-> (per-zone minima, maxima) of column col, as numpy arrays of dtype."""
+    n = gace_zonemap_info(zm)
+    lo = np.zeros(max(n, 1), dtype=dtype)
+    hi = np.zeros(max(n, 1), dtype=dtype)
+    _check(lib().gace_zonemap_read(zm, col, lo.ctypes.data, hi.ctypes.data))
+    return lo[:n], hi[:n]
+
+
+def gace_probe_selectivity_zm(ctx: int, table: Table, zm: int, preds, seed: int = 0, rate: float = 1.0,
+                              block_rows: int = 4096, stream=None):
+    """-> (counts, sampled_rows, kept_blocks, zones_skipped)"""
+    keep = _Keep()
+    t, p, s = _sel_args(table, preds, seed, rate, block_rows, keep)
+    counts = np.zeros(max(len(preds), 1), dtype=np.uint64)
+    info = gace_probe_info()
+    sk = ctypes.c_uint64()
+    _check(lib().gace_probe_selectivity_zm(ctx, ctypes.byref(t), zm, ctypes.byref(p), ctypes.byref(s),
+                                           counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                           ctypes.byref(info), ctypes.byref(sk), _stream_handle(stream)))
+    return counts[:len(preds)], int(info.sampled_rows), int(info.kept_blocks), int(sk.value)

@@ -17,6 +17,8 @@
 // running workgroup and the waits always end.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "plan.h"
 
 namespace gace {
@@ -534,11 +536,26 @@ __device__ __forceinline__ void scan_item(const BatchArgs& a, const PlanHdr& H, 
             }
         }
         __syncthreads();
+        // zone map: kept blocks on which no predicate can hold are sampled
+        // (counted above) but not scanned
+        unsigned long long scan_keep = keep;
+        if (S.zskip) {
+            const GACE_GLOBAL uint32_t* zs = (const GACE_GLOBAL uint32_t*)S.zskip;
+            bool skip = false;
+            if ((keep >> lane) & 1ull) {
+                const uint64_t r0 = (cb + (uint64_t)lane) * B;
+                const uint64_t r1 = (r0 + B < S.n_rows ? r0 + B : S.n_rows) - 1;
+                skip = true;
+                for (uint64_t z = r0 >> kZoneLog2; z <= (r1 >> kZoneLog2) && skip; ++z)
+                    skip = (zs[z >> 5] >> (z & 31)) & 1u;
+            }
+            scan_keep = keep & ~__ballot(skip);
+        }
         // group-major: group g streams every kept block whose requests reach
         // into it, each block with its own active bits
         {
             for (uint32_t g = 0;; ++g) {
-                const unsigned long long blocks_g = __ballot(((keep >> lane) & 1ull) && s_act[lane] > g * 64);
+                const unsigned long long blocks_g = __ballot(((scan_keep >> lane) & 1ull) && s_act[lane] > g * 64);
                 if (!blocks_g) break;
                 const GroupDesc G = cgroup(groups + g);
                 uint32_t cnt;
@@ -1683,9 +1700,169 @@ __global__ void __launch_bounds__(kWG) gace_sample_mask_kernel(uint64_t n_blocks
     mask[w] = bits;
 }
 
+// ------------------------------------------------------------------ zone maps
+// Per column and zone of kZoneRows rows: the smallest and largest value (for
+// float32: of the non-NaN values; an all-NaN zone gets min = +inf, max = -inf,
+// which no condition overlaps).  One workgroup per zone; each lane reads
+// 16-byte quads, coalesced across the wave, folding into min / max started at
+// the type's extremes, then wave shuffles and one LDS step reduce them.
+template <typename T> struct ZoneLim;
+template <> struct ZoneLim<int32_t> {
+    static __device__ int32_t lo() { return 0x7FFFFFFF; }
+    static __device__ int32_t hi() { return (int32_t)0x80000000; }
+};
+template <> struct ZoneLim<int64_t> {
+    static __device__ int64_t lo() { return 0x7FFFFFFFFFFFFFFFll; }
+    static __device__ int64_t hi() { return (int64_t)0x8000000000000000ull; }
+};
+template <> struct ZoneLim<float> {
+    static __device__ float lo() { return __builtin_huge_valf(); }
+    static __device__ float hi() { return -__builtin_huge_valf(); }
+};
+
+template <typename T>
+__device__ __forceinline__ void zone_fold(T x, T& lo, T& hi) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (x != x) return;   // NaN satisfies no condition
+    }
+    lo = x < lo ? x : lo;
+    hi = x > hi ? x : hi;
+}
+
+template <typename T>
+__device__ void zone_minmax(const T* col, uint64_t n_rows, T* zmin, T* zmax, uint8_t* lds) {
+    constexpr uint32_t kPerQuad = 16 / sizeof(T);
+    constexpr uint32_t kQuadsPerZone = (uint32_t)(kZoneRows / kPerQuad);
+    const uint64_t z = blockIdx.x;
+    const uint64_t r0 = z * kZoneRows;
+    T lo = ZoneLim<T>::lo(), hi = ZoneLim<T>::hi();
+    for (uint32_t q = threadIdx.x; q < kQuadsPerZone; q += kWG) {
+        const uint64_t r = r0 + (uint64_t)q * kPerQuad;
+        if (r + kPerQuad <= n_rows) {
+            const u32x4 v = __builtin_nontemporal_load((const GACE_GLOBAL u32x4*)(col + r));
+            T e[kPerQuad];
+            __builtin_memcpy(e, &v, 16);
+#pragma unroll
+            for (uint32_t i = 0; i < kPerQuad; ++i) zone_fold(e[i], lo, hi);
+        } else {
+            for (uint64_t i = r; i < n_rows; ++i) zone_fold(col[i], lo, hi);
+        }
+    }
+    for (int o = 32; o; o >>= 1) {
+        const T l2 = __shfl_xor(lo, o), h2 = __shfl_xor(hi, o);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+    }
+    T* s_lo = (T*)lds;
+    T* s_hi = s_lo + kWaves;
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[threadIdx.x >> 6] = lo;
+        s_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            lo = s_lo[w] < lo ? s_lo[w] : lo;
+            hi = s_hi[w] > hi ? s_hi[w] : hi;
+        }
+        zmin[z] = lo;
+        zmax[z] = hi;
+    }
+}
+
+__global__ void __launch_bounds__(kWG) gace_zone_build_kernel(const void* col, uint32_t dtype, uint64_t n_rows,
+                                                              void* zmin, void* zmax) {
+    __shared__ __align__(16) uint8_t lds[2 * kWaves * 8];
+    if (dtype == 2u)
+        zone_minmax<int64_t>((const int64_t*)col, n_rows, (int64_t*)zmin, (int64_t*)zmax, lds);
+    else if (dtype == 3u)
+        zone_minmax<float>((const float*)col, n_rows, (float*)zmin, (float*)zmax, lds);
+    else
+        zone_minmax<int32_t>((const int32_t*)col, n_rows, (int32_t*)zmin, (int32_t*)zmax, lds);
+}
+
+// one column's zone arrays, as the prune kernel reads them
+struct ZoneCol {
+    const void* zmin;
+    const void* zmax;
+    uint32_t dtype;
+    uint32_t reserved;
+};
+
+// a term of the request (the ABI's gace_term layout)
+struct ZTerm {
+    uint32_t col, op, n_vals, reserved;
+    int64_t v[8];
+};
+
+// can some value in [lo, hi] satisfy the term?  Integers compare in int64,
+// floats as IEEE binary32 (an empty float zone has lo > hi and fails every test)
+__device__ __forceinline__ bool zterm_may(const ZTerm& t, const ZoneCol& c, uint64_t z) {
+    if (c.dtype == 3u) {
+        const float lo = ((const float*)c.zmin)[z], hi = ((const float*)c.zmax)[z];
+        auto fv = [&](int k) { return __uint_as_float((uint32_t)(uint64_t)t.v[k]); };
+        if (t.op == 1u) return hi >= fv(0) && lo < fv(1) && lo <= hi;
+        for (uint32_t k = 0; k < t.n_vals; ++k)
+            if (lo <= fv(k) && fv(k) <= hi) return true;
+        return false;
+    }
+    int64_t lo, hi;
+    if (c.dtype == 2u) {
+        lo = ((const int64_t*)c.zmin)[z];
+        hi = ((const int64_t*)c.zmax)[z];
+    } else {
+        lo = ((const int32_t*)c.zmin)[z];
+        hi = ((const int32_t*)c.zmax)[z];
+    }
+    if (t.op == 1u) return hi >= t.v[0] && lo < t.v[1];
+    for (uint32_t k = 0; k < t.n_vals; ++k)
+        if (lo <= t.v[k] && t.v[k] <= hi) return true;
+    return false;
+}
+
+// bit z of skip: no predicate can hold on zone z.  One thread per zone; each
+// wave's 64 bits are written as two whole 32-bit words.
+__global__ void __launch_bounds__(kWG) gace_zone_prune_kernel(const ZoneCol* zc, const ZTerm* terms,
+                                                              const uint32_t* pred_off, uint32_t n_preds,
+                                                              uint64_t n_zones, uint32_t* skip) {
+    const uint64_t z = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    bool may = false;
+    if (z < n_zones) {
+        for (uint32_t p = 0; p < n_preds && !may; ++p) {
+            bool all = true;
+            for (uint32_t i = pred_off[p]; i < pred_off[p + 1] && all; ++i) all = zterm_may(terms[i], zc[terms[i].col], z);
+            may = all;
+        }
+    }
+    const unsigned long long sk = __ballot(z < n_zones && !may);
+    const uint64_t w0 = (z >> 6) * 2;                    // first 32-bit word of this wave
+    if ((threadIdx.x & 63) == 0 && w0 * 32 < n_zones) {
+        skip[w0] = (uint32_t)sk;
+        if ((w0 + 1) * 32 < n_zones) skip[w0 + 1] = (uint32_t)(sk >> 32);
+    }
+}
+
 }  // namespace gace
 
 extern "C" {
+
+hipError_t gace_launch_zone_build(const void* col, uint32_t dtype, uint64_t n_rows, void* zmin, void* zmax,
+                                  hipStream_t stream) {
+    const uint64_t zones = (n_rows + gace::kZoneRows - 1) / gace::kZoneRows;
+    if (zones == 0) return hipSuccess;
+    hipLaunchKernelGGL(gace::gace_zone_build_kernel, dim3((uint32_t)zones), dim3(gace::kWG), 0, stream, col, dtype,
+                       n_rows, zmin, zmax);
+    return hipGetLastError();
+}
+
+hipError_t gace_launch_zone_prune(const void* zc, const void* terms, const uint32_t* pred_off, uint32_t n_preds,
+                                  uint64_t n_zones, uint32_t* skip, hipStream_t stream) {
+    const uint64_t grid = (n_zones + gace::kWG - 1) / gace::kWG;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(gace::gace_zone_prune_kernel, dim3((uint32_t)grid), dim3(gace::kWG), 0, stream,
+                       (const gace::ZoneCol*)zc, (const gace::ZTerm*)terms, pred_off, n_preds, n_zones, skip);
+    return hipGetLastError();
+}
 
 hipError_t gace_launch_sample_mask(uint64_t n_blocks, uint64_t seed, uint32_t table_id, uint64_t thr, void* mask,
                                    hipStream_t stream) {

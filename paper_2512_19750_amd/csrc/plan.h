@@ -69,7 +69,13 @@ struct ScanDesc {
     uint32_t req_begin, n_req;    // thresholds sorted descending (reqthr) and bit prefix sums (reqcum)
     uint32_t hist_off;            // (n_req + 1) x 2 u64: rows, blocks by number of active requests
     uint32_t row_bytes;           // bytes per row over the referenced columns
+    uint64_t zskip;               // device address of a zone-skip bit map (bit z set: no predicate of the
+                                  // scan can hold on zone z, kZoneRows rows); 0: no zone map
+    uint64_t n_zones;
 };
+
+constexpr uint32_t kZoneLog2 = 12;                     // zone-map zones of 4096 rows
+constexpr uint64_t kZoneRows = 1ull << kZoneLog2;
 
 // 64 predicate bits of one scan (bits are in request order, requests sorted by
 // threshold descending, so the bits active on a block are a prefix)

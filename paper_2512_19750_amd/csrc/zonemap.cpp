@@ -1,0 +1,248 @@
+// zonemap.cpp -- zone maps (per-zone min / max of every column) and the
+// selectivity probe that skips zones on which no predicate can hold.
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gace_zone.h"
+#include "compile.h"
+#include "runtime.h"
+
+extern "C" {
+hipError_t gace_launch_zone_build(const void* col, uint32_t dtype, uint64_t n_rows, void* zmin, void* zmax,
+                                  hipStream_t stream);
+hipError_t gace_launch_zone_prune(const void* zc, const void* terms, const uint32_t* pred_off, uint32_t n_preds,
+                                  uint64_t n_zones, uint32_t* skip, hipStream_t stream);
+}
+
+using gace::set_error;
+
+struct gace_zonemap {
+    int device = 0;
+    uint64_t n_rows = 0, n_zones = 0;
+    uint32_t n_cols = 0;
+    std::vector<const void*> data;     // the columns it describes
+    std::vector<uint32_t> dtype;
+    uint8_t* d_mem = nullptr;          // per column: min[n_zones], max[n_zones]; then the ZoneCol array
+    std::vector<uint64_t> off;         // byte offset of column c's minima (maxima follow)
+    uint64_t zc_off = 0;
+};
+
+namespace {
+
+// layout of the kernels' per-column record
+struct ZoneColHost {
+    const void* zmin;
+    const void* zmax;
+    uint32_t dtype;
+    uint32_t reserved;
+};
+
+uint64_t width(uint32_t dtype) { return dtype == GACE_I64 ? 8 : 4; }
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+gace_status hip_err(hipError_t e, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return GACE_EDEVICE;
+}
+
+#define ZTRY(expr, what)                               \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_err(e_, what); \
+    } while (0)
+
+}  // namespace
+
+extern "C" gace_status gace_zonemap_build(gace_ctx* ctx, const gace_table* table, gace_zonemap** out, void* stream) {
+    if (!ctx || !table || !out) {
+        set_error("NULL argument");
+        return GACE_EINVAL;
+    }
+    gace_predicates none;
+    std::memset(&none, 0, sizeof(none));
+    gace_sample_spec sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.rate = 1.0;
+    sp.block_rows = 4096;
+    std::string msg;
+    if (gace_status st = gace::check_selectivity(table, &none, &sp, msg)) {
+        set_error(msg);
+        return st;
+    }
+    ZTRY(hipSetDevice(ctx->device), "set device");
+    gace_zonemap* zm = new gace_zonemap();
+    zm->device = ctx->device;
+    zm->n_rows = table->n_rows;
+    zm->n_zones = (table->n_rows + GACE_ZONE_ROWS - 1) / GACE_ZONE_ROWS;
+    zm->n_cols = table->n_cols;
+    uint64_t bytes = 0;
+    std::vector<ZoneColHost> zc(table->n_cols);
+    for (uint32_t c = 0; c < table->n_cols; ++c) {
+        zm->data.push_back(table->cols[c].data);
+        zm->dtype.push_back(table->cols[c].dtype);
+        zm->off.push_back(bytes);
+        bytes += 2 * align256(zm->n_zones * width(table->cols[c].dtype));
+    }
+    zm->zc_off = bytes;
+    bytes += align256(std::max<size_t>(1, zc.size()) * sizeof(ZoneColHost));
+    hipError_t e = hipMalloc((void**)&zm->d_mem, bytes);
+    if (e != hipSuccess) {
+        delete zm;
+        set_error("zone map allocation of " + std::to_string(bytes) + " bytes failed");
+        return GACE_ENOMEM;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    for (uint32_t c = 0; c < table->n_cols; ++c) {
+        const uint64_t w = width(zm->dtype[c]);
+        uint8_t* mn = zm->d_mem + zm->off[c];
+        uint8_t* mx = mn + align256(zm->n_zones * w);
+        zc[c].zmin = mn;
+        zc[c].zmax = mx;
+        zc[c].dtype = zm->dtype[c];
+        zc[c].reserved = 0;
+        e = gace_launch_zone_build(table->cols[c].data, zm->dtype[c], zm->n_rows, mn, mx, st);
+        if (e != hipSuccess) {
+            gace_zonemap_destroy(zm);
+            return hip_err(e, "zone map kernel");
+        }
+    }
+    if (!zc.empty()) {
+        e = hipMemcpyAsync(zm->d_mem + zm->zc_off, zc.data(), zc.size() * sizeof(ZoneColHost), hipMemcpyHostToDevice,
+                           st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    } else {
+        e = hipStreamSynchronize(st);
+    }
+    if (e != hipSuccess) {
+        gace_zonemap_destroy(zm);
+        return hip_err(e, "zone map upload");
+    }
+    *out = zm;
+    return GACE_OK;
+}
+
+extern "C" gace_status gace_zonemap_destroy(gace_zonemap* zm) {
+    if (!zm) return GACE_OK;
+    (void)hipSetDevice(zm->device);
+    if (zm->d_mem) (void)hipFree(zm->d_mem);
+    delete zm;
+    return GACE_OK;
+}
+
+extern "C" gace_status gace_zonemap_info(const gace_zonemap* zm, uint64_t* n_zones) {
+    if (!zm || !n_zones) {
+        set_error("NULL argument");
+        return GACE_EINVAL;
+    }
+    *n_zones = zm->n_zones;
+    return GACE_OK;
+}
+
+extern "C" gace_status gace_zonemap_read(const gace_zonemap* zm, uint32_t col, void* zmin, void* zmax) {
+    if (!zm || col >= zm->n_cols || (zm->n_zones && (!zmin || !zmax))) {
+        set_error("zone map read needs a zone map, a column index in range and two host arrays");
+        return GACE_EINVAL;
+    }
+    ZTRY(hipSetDevice(zm->device), "set device");
+    const uint64_t b = zm->n_zones * width(zm->dtype[col]);
+    const uint8_t* mn = zm->d_mem + zm->off[col];
+    if (b) {
+        ZTRY(hipMemcpy(zmin, mn, b, hipMemcpyDeviceToHost), "zone map download");
+        ZTRY(hipMemcpy(zmax, mn + align256(b), b, hipMemcpyDeviceToHost), "zone map download");
+    }
+    return GACE_OK;
+}
+
+extern "C" gace_status gace_probe_selectivity_zm(gace_ctx* ctx, const gace_table* table, const gace_zonemap* zm,
+                                                 const gace_predicates* preds, const gace_sample_spec* spec,
+                                                 uint64_t* counts, gace_probe_info* info, uint64_t* zones_skipped,
+                                                 void* stream) {
+    if (!ctx || !table || !zm || !preds) {
+        set_error("NULL argument");
+        return GACE_EINVAL;
+    }
+    gace_request r;
+    std::memset(&r, 0, sizeof(r));
+    r.kind = GACE_REQ_SELECTIVITY;
+    r.table = *table;
+    r.preds = *preds;
+    if (spec) {
+        r.spec = *spec;
+    } else {
+        r.spec.rate = 1.0;
+        r.spec.block_rows = 4096;
+    }
+    r.counts = counts;
+    r.info = info;
+    std::string msg;
+    if (gace_status st = gace::check_request(&r, msg)) {
+        set_error(msg);
+        return st;
+    }
+    bool same = zm->n_rows == table->n_rows && zm->n_cols == table->n_cols && zm->device == ctx->device;
+    for (uint32_t c = 0; same && c < table->n_cols; ++c)
+        same = zm->data[c] == table->cols[c].data && zm->dtype[c] == table->cols[c].dtype;
+    if (!same) {
+        set_error("the zone map was built for another table (rows, column addresses or types differ)");
+        return GACE_EINVAL;
+    }
+    const uint32_t np = preds->n_preds, nt = np ? preds->pred_off[np] : 0;
+    const uint64_t skip_b = align256((zm->n_zones + 31) / 32 * 4);
+    const uint64_t term_b = align256((uint64_t)std::max<uint32_t>(nt, 1) * sizeof(gace_term));
+    const uint64_t off_b = align256(((uint64_t)np + 1) * 4);
+    const uint64_t need = skip_b + term_b + off_b;
+    if (need > ctx->arena_bytes) {
+        set_error("workspace too small for the zone-skip map: need " + std::to_string(need) + " bytes");
+        return GACE_ENOMEM;
+    }
+    ZTRY(hipSetDevice(ctx->device), "set device");
+    if (ctx->h_hp_bytes < need) {
+        if (ctx->h_hp) (void)hipHostFree(ctx->h_hp);
+        ctx->h_hp = nullptr;
+        ctx->h_hp_bytes = 0;
+        ZTRY(hipHostMalloc((void**)&ctx->h_hp, need, hipHostMallocDefault), "pinned staging");
+        ctx->h_hp_bytes = need;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t* d_skip = (uint32_t*)ctx->d_arena_base;
+    uint8_t* d_terms = ctx->d_arena_base + skip_b;
+    uint32_t* d_off = (uint32_t*)(d_terms + term_b);
+    if (nt) std::memcpy(ctx->h_hp + skip_b, preds->terms, (uint64_t)nt * sizeof(gace_term));
+    if (np) std::memcpy(ctx->h_hp + skip_b + term_b, preds->pred_off, ((uint64_t)np + 1) * 4);
+    ZTRY(hipMemcpyAsync(d_terms, ctx->h_hp + skip_b, term_b + off_b, hipMemcpyHostToDevice, st), "term upload");
+    ZTRY(gace_launch_zone_prune(zm->d_mem + zm->zc_off, d_terms, d_off, np, zm->n_zones, d_skip, st),
+         "zone prune kernel");
+
+    gace::CompileOptions opt;
+    opt.item_rows = ctx->sched.item_rows;
+    opt.join_part_keys = ctx->sched.join_part_keys;
+    gace::CompiledBatch cb;
+    gace::compile_batch(&r, 1, opt, cb);
+    if (cb.status[0] != GACE_OK) {
+        set_error(cb.errors[0]);
+        return cb.status[0];
+    }
+    if (cb.scans.size() == 1) {
+        gace::PlanHdr H;
+        std::memcpy(&H, cb.plan.data(), sizeof(H));
+        gace::ScanDesc* sd = (gace::ScanDesc*)(cb.plan.data() + H.scans_off);
+        sd->zskip = (uint64_t)(uintptr_t)d_skip;
+        sd->n_zones = zm->n_zones;
+        cb.scans[0].zskip = sd->zskip;
+        cb.scans[0].n_zones = sd->n_zones;
+    }
+    if (!cb.sel.empty()) {
+        if (gace_status e = gace::run_compiled(ctx, cb, &r, nullptr, st, false)) return e;
+    }
+    if (zones_skipped) {
+        ZTRY(hipStreamSynchronize(st), "synchronize");
+        std::vector<uint32_t> bits((zm->n_zones + 31) / 32);
+        if (!bits.empty())
+            ZTRY(hipMemcpy(bits.data(), d_skip, bits.size() * 4, hipMemcpyDeviceToHost), "skip map download");
+        uint64_t n = 0;
+        for (uint32_t w : bits) n += (uint64_t)__builtin_popcount(w);
+        *zones_skipped = n;
+    }
+    return GACE_OK;
+}
