@@ -697,7 +697,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     std::vector<Item> scan_items;
     std::vector<double> item_cost;
     for (uint32_t s = 0; s < scans.size(); ++s) {
-        const ScanDesc& S = scans[s];
+        ScanDesc& S = scans[s];
         const uint32_t* rc = rcum_flat.data() + S.req_begin;
         const uint64_t* rt = rthr_flat.data() + S.req_begin;
         double gpb = 0.0;
@@ -708,9 +708,22 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         }
         if (gpb < 1.0) gpb = 1.0;
         const uint32_t rows = std::max<uint32_t>(1024u, (uint32_t)((double)opt.item_rows / gpb));
-        const uint64_t bb = bpi_for(S.thr_max, S.log2B, rows);
+        if (S.thr_max == 0) continue;
+        // one request on blocks under 4096 rows, with more than one kept block per 4096 rows
+        // expected (thr_max / 2^32 > B / 4096): decided row by row in whole
+        // tiles, which read every row of the item, so items are sized by rows
+        // and cut on tile boundaries
+        S.fine = S.n_req == 1 && S.log2B < kZoneLog2 && S.thr_max > (1ull << (S.log2B + 20)) ? 1u : 0u;
+        uint64_t bb;
+        if (S.fine) {
+            const uint64_t per_tile = kZoneRows >> S.log2B;
+            const uint64_t want = std::max<uint64_t>(kZoneRows, rows) >> S.log2B;
+            bb = (want + per_tile - 1) / per_tile * per_tile;
+        } else {
+            bb = bpi_for(S.thr_max, S.log2B, rows);
+        }
         if (bb == 0) continue;
-        const double p = S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0;
+        const double p = S.fine ? 1.0 : S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0;
         for (uint64_t b = 0; b < S.n_blocks; b += bb) {
             Item it = {IT_SCAN, s, 0, 0, b, std::min(S.n_blocks, b + bb)};
             scan_items.push_back(it);

@@ -477,6 +477,113 @@ __device__ __forceinline__ void decide_blocks(uint64_t cb, uint64_t b_end, uint6
     }
 }
 
+// ------------------------------------------------------------------ fine scan
+// One request on blocks of fewer than 4096 rows, with at least one block in
+// 4096 / B kept on average: the item's rows are walked in aligned 4096-row
+// tiles and every row's block is decided by the lane that holds the row (one
+// Philox per distinct block of the lane's rows), so a tile costs one pass
+// however its kept blocks are spread.  A lane keeps a 16-bit mask of its kept
+// rows; the lane holding a block's first row counts the block.  Counts and
+// sample histogram equal the block-by-block path's.
+template <int AS>
+__device__ __forceinline__ void fine_group(const GACE_CONST ColProg* cols, const GroupDesc& G, const uint8_t* tab,
+                                           uint32_t g, uint32_t km, uint32_t all_bits, uint64_t q0, uint64_t r1,
+                                           int lane, uint32_t mode, uint32_t& cnt) {
+    const uint64_t active = G.base_mask & group_prefix(all_bits, g);
+    uint64_t m[kRows];
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) m[i] = ((km >> i) & 1u) ? active : 0ull;
+    for (uint32_t c = G.col_begin; c < G.col_end; ++c) {
+        const ColProg P = cprog(cols + c);
+        if (P.kind == CP_RANK64) {
+            lookup64<AS>(P, tab, q0, r1, m);
+        } else {
+            uint32_t v[kRows];
+            load32(P, q0, r1, v);
+            lookup32<AS>(P, tab, v, m);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) count_rows(m[i], active, cnt, lane, mode);
+}
+
+__device__ __forceinline__ void scan_fine(const BatchArgs& a, const ScanDesc& S, const GACE_CONST GroupDesc* groups,
+                                          const GACE_CONST ColProg* cols, const uint32_t* slots, uint32_t all_bits,
+                                          unsigned long long* s_hist, uint32_t* s_cnt, uint8_t* s_tab, int* s_staged,
+                                          uint32_t n_lds_groups, uint64_t b_begin, uint64_t b_end, int lane,
+                                          int wave) {
+    const uint32_t log2B = S.log2B;
+    const uint64_t B = 1ull << log2B;
+    const uint64_t r_begin = b_begin << log2B;
+    const uint64_t r_end = min(b_end << log2B, S.n_rows);
+    const uint64_t lane_off = (uint64_t)wave * 256 * kQuads + 4ull * (uint64_t)lane;
+    for (uint64_t t = r_begin; t < r_end; t += kZoneRows) {
+        const uint64_t q0 = t + lane_off;
+        const uint64_t r1 = t + kZoneRows < r_end ? t + kZoneRows : r_end;
+        uint32_t km = 0;   // bit i: row i of this lane is in a kept block
+        uint32_t hrows = 0, hblocks = 0;
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            const uint64_t r = q0 + 256ull * (i >> 2) + (i & 3);
+            // rows of one quad share a block when B >= 4: decide it once
+            if ((i & 3) == 0 || log2B < 2) {
+                bool kept = false;
+                if (r < r1) {
+                    kept = (uint64_t)block_word0(r >> log2B, S.table_id, S.seed) < S.thr_max;
+                    if (kept && (r & (B - 1)) == 0) {
+                        hrows += (uint32_t)((r + B < S.n_rows ? r + B : S.n_rows) - r);
+                        hblocks += 1;
+                    }
+                }
+                if (kept) km |= (log2B < 2 ? 1u : 15u) << i;
+            }
+        }
+        if (log2B >= 2) {   // drop the rows of a quad past the end
+#pragma unroll
+            for (int i = 0; i < kRows; ++i)
+                if (q0 + 256ull * (i >> 2) + (i & 3) >= r1) km &= ~(1u << i);
+        }
+        // the tile's kept rows and blocks, one LDS add per wave
+        for (int o = 32; o; o >>= 1) {
+            hrows += __shfl_xor(hrows, o);
+            hblocks += __shfl_xor(hblocks, o);
+        }
+        if (lane == 0 && hblocks) {
+            atomicAdd(&s_hist[2], (unsigned long long)hrows);
+            atomicAdd(&s_hist[3], (unsigned long long)hblocks);
+        }
+        if (S.zskip) {
+            const GACE_GLOBAL uint32_t* zs = (const GACE_GLOBAL uint32_t*)S.zskip;
+            const uint64_t z = t >> kZoneLog2;
+            if ((zs[z >> 5] >> (z & 31)) & 1u) continue;   // sampled, but no predicate can hold here
+        }
+        const bool any = km != 0;
+        for (uint32_t g = 0; g * 64 < all_bits; ++g) {
+            if (!__syncthreads_or(any)) break;
+            const GroupDesc G = cgroup(groups + g);
+            uint32_t cnt = 0;
+            if (G.tab_bytes <= kGroupTabBudget) {
+                if (*s_staged != (int)g) {
+                    __syncthreads();
+                    const uint4* src = (const uint4*)(a.plan + G.tab_off);
+                    uint4* dst = (uint4*)s_tab;
+                    for (uint32_t i = threadIdx.x; i < G.tab_bytes / 16; i += kWG) dst[i] = src[i];
+                    __syncthreads();
+                    if (threadIdx.x == 0) *s_staged = (int)g;
+                }
+                if (__ballot(any)) fine_group<3>(cols, G, s_tab, g, km, all_bits, q0, r1, lane, a.count_mode, cnt);
+            } else if (__ballot(any)) {
+                fine_group<1>(cols, G, a.plan + G.tab_off, g, km, all_bits, q0, r1, lane, a.count_mode, cnt);
+            }
+            if (cnt) {
+                if (g < n_lds_groups) atomicAdd(&s_cnt[g * 64 + lane], cnt);
+                else atomicAdd(&a.counts[slots[G.slot_index + lane]], (unsigned long long)cnt);
+            }
+            if (S.n_groups > 1) __syncthreads();   // the staged table may be replaced by the next group
+        }
+    }
+}
+
 // ------------------------------------------------------------------ scan item
 __device__ __forceinline__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, uint8_t* lds) {
     const ScanDesc S = ((const ScanDesc*)(a.plan + H.scans_off))[it.idx];
@@ -512,7 +619,10 @@ __device__ __forceinline__ void scan_item(const BatchArgs& a, const PlanHdr& H, 
     __syncthreads();
 
     const uint64_t B = 1ull << S.log2B;
-    for (uint64_t cb = it.begin; cb < it.end; cb += 64) {
+    if (S.fine)
+        scan_fine(a, S, groups, cols, slots, small ? s_cum[1] : rcum[1], s_hist, s_cnt, s_tab, s_staged,
+                  n_lds_groups, it.begin, it.end, lane, wave);
+    for (uint64_t cb = it.begin; cb < it.end && !S.fine; cb += 64) {
         decide_blocks(cb, it.end, S.thr_max, S.table_id, S.seed, s_w0, s_keep);
         __syncthreads();
         const unsigned long long keep = *s_keep;

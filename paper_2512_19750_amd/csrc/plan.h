@@ -72,6 +72,8 @@ struct ScanDesc {
     uint64_t zskip;               // device address of a zone-skip bit map (bit z set: no predicate of the
                                   // scan can hold on zone z, kZoneRows rows); 0: no zone map
     uint64_t n_zones;
+    uint32_t fine;                // blocks under 4096 rows decided row by row in whole tiles (items tile-aligned)
+    uint32_t reserved;
 };
 
 constexpr uint32_t kZoneLog2 = 12;                     // zone-map zones of 4096 rows

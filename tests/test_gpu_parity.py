@@ -110,6 +110,25 @@ def test_edge_values_vs_oracle(g, ctx, torch_dev, seed):
     assert got[0].tolist() == want[0].tolist()
 
 
+@pytest.mark.parametrize("B,rate", [(1, 0.3), (1, 0.0002), (2, 0.05), (8, 0.0015), (8, 0.003), (512, 0.2),
+                                    (2048, 0.45), (2048, 0.55)])
+def test_small_blocks_vs_oracle(g, ctx, torch_dev, B, rate):
+    """Blocks under 4096 rows on both sides of the switch between the
+    block-by-block scan and the row-by-row tile scan (one kept block per
+    4096 rows expected: rate = B / 4096), over two predicate groups, a
+    ragged last tile and a partial last block."""
+    rng = np.random.default_rng(B * 1000 + int(rate * 1e4))
+    n = 5 * 4096 * 3 + 1237
+    cols, dtypes = _edge_table(rng, n)
+    preds = _edge_preds(rng, 70)
+    _say("small blocks", B, rate)
+    table = g.Table(_tensors(cols, torch_dev), 61)
+    got = g.gace_probe_selectivity(ctx, table, preds, seed=5, rate=rate, block_rows=B)
+    want = oracle.probe_selectivity(cols, dtypes, 61, preds, 5, rate, B)
+    assert got[1:] == want[1:]
+    assert got[0].tolist() == want[0].tolist()
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_count_modes_agree(g, torch_dev, mode):
     rng = np.random.default_rng(5)
