@@ -696,6 +696,16 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     // costliest first, so the tail of the queue is short items.
     std::vector<Item> scan_items;
     std::vector<double> item_cost;
+    // a small batch (a single probe, a short served batch) still gets about
+    // four items per worker, down to items of 4096 rows
+    uint32_t item_rows = opt.item_rows;
+    if (opt.workers) {
+        double kept = 0.0;
+        for (const ScanDesc& S : scans)
+            kept += (double)S.n_rows * (S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0);
+        const double cap = std::max(4096.0, kept / (4.0 * opt.workers));
+        if (cap < item_rows) item_rows = (uint32_t)cap;
+    }
     for (uint32_t s = 0; s < scans.size(); ++s) {
         ScanDesc& S = scans[s];
         const uint32_t* rc = rcum_flat.data() + S.req_begin;
@@ -707,7 +717,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
             gpb += S.thr_max ? (double)rt[k] / (double)S.thr_max : 0.0;
         }
         if (gpb < 1.0) gpb = 1.0;
-        const uint32_t rows = std::max<uint32_t>(1024u, (uint32_t)((double)opt.item_rows / gpb));
+        const uint32_t rows = std::max<uint32_t>(1024u, (uint32_t)((double)item_rows / gpb));
         if (S.thr_max == 0) continue;
         // one request on blocks under 4096 rows, with more than one kept block per 4096 rows
         // expected (thr_max / 2^32 > B / 4096): decided row by row in whole

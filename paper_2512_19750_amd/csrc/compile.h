@@ -22,6 +22,7 @@ gace_status check_request(const gace_request* r, std::string& msg);
 struct CompileOptions {
     uint32_t item_rows = 65536;      // target sampled rows per work item
     uint32_t join_part_keys = 1024;  // expected sampled keys per join hash partition
+    uint32_t workers = 0;            // scan workgroups of the launch (0: items of item_rows regardless)
 };
 
 // host bookkeeping that maps plan results back to the requests

@@ -255,6 +255,7 @@ extern "C" gace_status gace_probe_selectivity_host(gace_ctx* ctx, const gace_tab
         gace::CompileOptions co;
         co.item_rows = ctx->sched.item_rows;
         co.join_part_keys = ctx->sched.join_part_keys;
+        co.workers = (uint32_t)ctx->n_cu * ctx->sched.wgs_per_cu;
         gace::CompiledBatch cb;
         gace::compile_batch(&r, 1, co, cb);
         if (cb.status[0] != GACE_OK) {

@@ -154,7 +154,6 @@ struct MergeEntry {
 // per-join device accumulators and phase counters (zeroed before each batch)
 struct JoinAcc {
     unsigned long long join, ndv[2], n[2], sent[2];
-    unsigned long long f1[2], f2[2];        // distinct keys seen exactly once / twice per side
     unsigned long long buf_off;             // arena offset of the partitioned keys (R then S)
     unsigned long long nkeys[2];            // sampled keys per side other than the sentinel value
     unsigned long long status;              // 0 ok, 2 arena exhausted, 3 aggregation stack overflow
@@ -163,6 +162,7 @@ struct JoinAcc {
     uint32_t next_unit, n_units;
     uint32_t hist_done, off_done, base_done, scatter_done, agg_done, s2_done;
     uint32_t next_s2, reserved;
+    unsigned long long f1[2], f2[2];        // distinct keys seen exactly once / twice per side
 };
 
 struct Arena {                              // bump allocator for partition buffers

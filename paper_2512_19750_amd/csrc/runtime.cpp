@@ -59,8 +59,8 @@ static gace_schedule default_schedule() {
     gace_schedule s;
     std::memset(&s, 0, sizeof(s));
     s.wg_threads = 256;
-    s.wgs_per_cu = 2;
-    s.item_rows = 131072;
+    s.wgs_per_cu = 3;
+    s.item_rows = 262144;
     s.count_mode = 0;
     s.join_part_keys = 1024;
     s.join_wgs_per_cu = 2;
@@ -278,6 +278,7 @@ gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace
     CompileOptions opt;
     opt.item_rows = c->sched.item_rows;
     opt.join_part_keys = c->sched.join_part_keys;
+    opt.workers = (uint32_t)c->n_cu * c->sched.wgs_per_cu;
     CompiledBatch cb;
     compile_batch(reqs, n, opt, cb);
     gace_status first = GACE_OK;

@@ -153,6 +153,7 @@ bool gace_server::try_launch(ServeSlot& s, std::unique_lock<std::mutex>& lk) {
     gace::CompileOptions opt;
     opt.item_rows = s.ctx->sched.item_rows;
     opt.join_part_keys = s.ctx->sched.join_part_keys;
+    opt.workers = (uint32_t)s.ctx->n_cu * s.ctx->sched.wgs_per_cu;
     gace::compile_batch(s.arr.data(), (uint32_t)s.arr.size(), opt, s.cb);
     gace_status st = gace::launch_compiled(s.ctx, s.cb, s.stream, true);
     lk.lock();

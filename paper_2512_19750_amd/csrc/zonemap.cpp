@@ -217,6 +217,7 @@ extern "C" gace_status gace_probe_selectivity_zm(gace_ctx* ctx, const gace_table
     gace::CompileOptions opt;
     opt.item_rows = ctx->sched.item_rows;
     opt.join_part_keys = ctx->sched.join_part_keys;
+    opt.workers = (uint32_t)ctx->n_cu * ctx->sched.wgs_per_cu;
     gace::CompiledBatch cb;
     gace::compile_batch(&r, 1, opt, cb);
     if (cb.status[0] != GACE_OK) {
