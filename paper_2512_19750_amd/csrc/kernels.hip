@@ -1307,7 +1307,7 @@ __device__ __forceinline__ void agg_size(AggLds& T, uint64_t n, uint32_t cap) {
 // of the table the pass is abandoned (the spare quarter absorbs the keys
 // inserted before the count catches up) and redone on split residue classes;
 // so is a pass that finds the table full.
-constexpr int kAggBatch = 4;
+constexpr int kAggBatch = 2;
 
 // Probe kAggBatch entries per lane into the table.  Slots are paired into
 // buckets read with one 16-byte LDS load: an entry matches either slot of
@@ -1758,7 +1758,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))
 
 // join aggregation (queue 2: items [n_join_end, n_items)); launched after
 // the partitioning kernel on the same stream, so every partition is final
-__global__ void __launch_bounds__(kWG) gace_agg_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) gace_agg_kernel(BatchArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ uint32_t s_item;
     const PlanHdr H = *(const PlanHdr*)a.plan;

@@ -64,7 +64,7 @@ static gace_schedule default_schedule() {
     s.count_mode = 0;
     s.join_part_keys = 1024;
     s.join_wgs_per_cu = 2;
-    s.agg_wgs_per_cu = 3;
+    s.agg_wgs_per_cu = 4;
     return s;
 }
 
