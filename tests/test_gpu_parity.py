@@ -337,6 +337,48 @@ def test_batch_matches_oracle_and_plain(g, ctx, torch_dev):
             assert g.gace_join_freq(ctx, q.R, q.S) == want
 
 
+def test_config4_full_batch_sampled(g, torch_dev):
+    """The benchmark's workload at full size (16 tables, 448 selectivity and
+    64 join requests, 50 GB resident), run as one batch by direct launch like
+    the timed steps: every request equals its plain-path result, and a sample
+    of requests (the cheapest for the host, two at the median and one at the
+    90th percentile of host cost) equals the oracle's."""
+    import torch
+    w = datagen.config4()
+    tabs, keys = _materialise(w, torch_dev)
+    torch.cuda.synchronize()
+    reqs = _requests(g, w, tabs, keys)
+    free_b, _ = torch.cuda.mem_get_info()
+    c = g.gace_create(0, int(min(free_b * 0.6, 48 << 30)))     # the benchmark's workspace
+    try:
+        g.gace_set_graph(c, False)
+        _say("config4 full batch")
+        assert all(s == 0 for s in g.gace_batch_run(c, reqs))
+        assert g.gace_last_kernel_stats(c)["timed"]
+        for q in reqs:
+            if isinstance(q, g.JoinRequest):
+                assert g.gace_join_freq(c, q.R, q.S) == q.result()
+            else:
+                alone = g.gace_probe_selectivity(c, q.table, q.preds, q.seed, q.rate, q.block_rows)
+                assert alone[0].tolist() == q.result()[0].tolist() and alone[1:] == q.result()[1:]
+    finally:
+        g.gace_destroy(c)
+    sel = [(i, w.tables[r.table].n_rows * r.spec.rate * len(r.preds)) for i, r in enumerate(w.sel)]
+    sel.sort(key=lambda x: x[1])
+    picks = [i for i, _ in sel[:6]] + [sel[len(sel) // 2][0], sel[len(sel) // 2 + 1][0], sel[9 * len(sel) // 10][0]]
+    pos = {key: k for k, key in enumerate(w.order)}
+    for i in picks:
+        _say("config4 oracle sel", i)
+        want = oracle.sel_request(w, i, nthreads=16)
+        got = reqs[pos[("sel", i)]].result()
+        assert got[0].tolist() == want[0].tolist() and got[1:] == want[1:], i
+    joins = sorted(range(len(w.joins)), key=lambda j: w.joins[j].r.n_rows * w.joins[j].spec_r.rate +
+                   w.joins[j].s.n_rows * w.joins[j].spec_s.rate)
+    for j in joins[:2]:
+        _say("config4 oracle join", j)
+        assert reqs[pos[("join", j)]].result() == oracle.join_request(w, j, nthreads=16), j
+
+
 def test_batch_repeatable_and_schedules_agree(g, torch_dev):
     w = datagen.config4(scale=0.002, n_sel=64, n_join=6, seed_offset=3)
     tabs, keys = _materialise(w, torch_dev)
