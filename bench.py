@@ -630,6 +630,9 @@ def main():
     ctx = g.gace_create(0, ws)
     reqs = build_requests(g, w, tabs, keys)
     prepared = g.make_requests(reqs)
+    # the timed region launches directly (below), so the schedule is tuned
+    # in that launch mode
+    g.gace_set_graph(ctx, False)
     if args.autotune:
         t0 = time.time()
         g.gace_autotune(ctx, reqs, args.tune_cache)
@@ -642,7 +645,7 @@ def main():
     for _ in range(args.warmup):
         g.gace_batch_run(ctx, reqs, prepared=prepared)
     torch.cuda.synchronize()
-    kms, sms, jms = [], [], []
+    kms, sms, jms, cms = [], [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g.gace_batch_run(ctx, reqs, prepared=prepared)
@@ -650,6 +653,7 @@ def main():
         ks = g.gace_last_kernel_stats(ctx)
         sms.append(ks["scan_ms"])
         jms.append(ks["join_ms"])
+        cms.append(ks["compile_ms"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = g.gace_last_batch_stats(ctx)
@@ -687,9 +691,11 @@ def main():
             join_keys += r["n_R"] + r["n_S"]
         else:
             sel_rows += q.result()[1]
-    print("[bench] batch %.2f ms/step (kernels %.2f ms: scan %.2f, join %.2f; graph replay %.2f ms/step), "
-          "%.3g rows*preds/s" % (ms_step, kernel_ms, per_kernel["gace_scan_kernel"]["ms"],
-                                 per_kernel["gace_join_stage"]["ms"], graph_ms, value), file=sys.stderr, flush=True)
+    compile_ms = sum(cms) / len(cms)
+    print("[bench] batch %.2f ms/step (host compile %.2f ms, kernels %.2f ms: scan %.2f, join %.2f; graph replay "
+          "%.2f ms/step), %.3g rows*preds/s" % (ms_step, compile_ms, kernel_ms, per_kernel["gace_scan_kernel"]["ms"],
+                                               per_kernel["gace_join_stage"]["ms"], graph_ms, value),
+          file=sys.stderr, flush=True)
 
     plain = None
     gate = None
@@ -780,6 +786,7 @@ def main():
                              "traffic": stored_traffic(k)}, **({"kernels": v["kernels"]} if "kernels" in v else {}))
                     for k, v in per_kernel.items()},
         "batch_kernel_span_ms": round(kernel_ms, 4),
+        "host_compile_ms": round(compile_ms, 4),
         "graph_replay_ms_per_step": round(graph_ms, 4),
         "join_keys_per_s": join_keys / (wall / args.steps),
         "served": served,

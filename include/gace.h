@@ -218,9 +218,10 @@ gace_status gace_join_freq(gace_ctx* ctx, const gace_keys* R, const gace_keys* S
 gace_status gace_batch_run(gace_ctx* ctx, const gace_request* reqs, uint32_t n, gace_status* per_req,
                            void* stream);
 
-/* Time candidate schedules on this request mix and keep the fastest for its
-   shape bucket in the context; cache_path (may be NULL) is a JSON file read
-   before and written after the search. */
+/* Time candidate schedules on this request mix, in the context's launch
+   mode (gace_set_graph), and keep the fastest for its shape bucket in the
+   context; cache_path (may be NULL) is a JSON file read before and written
+   after the search, keyed by device, kernels, launch mode and shape. */
 gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, const char* cache_path,
                           void* stream);
 gace_status gace_get_schedule(gace_ctx* ctx, gace_schedule* out);
@@ -241,12 +242,14 @@ gace_status gace_last_batch_stats(gace_ctx* ctx, double* kernel_ms, uint64_t* al
    stream where it runs concurrently; with the algorithmic HBM bytes of each
    (scan: kept rows x referenced column widths per shared scan; join: 8 bytes
    per sampled key + 16 bytes per distinct key and side).
-   timed = 0 and both times 0 after a graph-replayed batch. */
+   timed = 0 and both times 0 after a graph-replayed batch.  compile_ms is
+   the host time spent validating and compiling the batch's requests into
+   the device plan (either launch mode). */
 typedef struct {
     double scan_ms, join_ms;
     uint64_t scan_alg_bytes, join_alg_bytes;
     uint32_t timed;
-    uint32_t reserved;
+    float compile_ms;
 } gace_kernel_stats;
 
 gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out);

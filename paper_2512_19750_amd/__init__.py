@@ -99,7 +99,7 @@ class gace_trace_rec(ctypes.Structure):
 
 class gace_kernel_stats(ctypes.Structure):
     _fields_ = [("scan_ms", ctypes.c_double), ("join_ms", ctypes.c_double), ("scan_alg_bytes", ctypes.c_uint64),
-                ("join_alg_bytes", ctypes.c_uint64), ("timed", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("join_alg_bytes", ctypes.c_uint64), ("timed", ctypes.c_uint32), ("compile_ms", ctypes.c_float)]
 
 
 class gace_server_cfg(ctypes.Structure):
@@ -534,7 +534,7 @@ def gace_last_kernel_stats(ctx: int) -> dict:
     k = gace_kernel_stats()
     _check(lib().gace_last_kernel_stats(ctx, ctypes.byref(k)))
     return dict(timed=bool(k.timed), scan_ms=k.scan_ms, join_ms=k.join_ms, scan_alg_bytes=int(k.scan_alg_bytes),
-                join_alg_bytes=int(k.join_alg_bytes))
+                join_alg_bytes=int(k.join_alg_bytes), compile_ms=float(k.compile_ms))
 
 
 def gace_set_graph(ctx: int, enable: bool = True):

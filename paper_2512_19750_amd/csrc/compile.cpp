@@ -429,7 +429,17 @@ static uint64_t bpi_for(uint64_t thr, uint32_t log2B, uint32_t item_rows) {
 }
 
 void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& opt, CompiledBatch& out) {
-    out = CompiledBatch();
+    // clear, keeping the vectors' capacity: a context compiles batch after
+    // batch, and fresh multi-megabyte buffers cost more in page faults than
+    // the compilation itself
+    out.plan.clear();
+    out.items.clear();
+    out.sel.clear();
+    out.joins.clear();
+    out.scans.clear();
+    out.jdesc.clear();
+    out.n_counts = out.n_hist = 0;
+    out.arena_static = 0;
     out.status.assign(n, GACE_OK);
     out.errors.assign(n, std::string());
 

@@ -279,8 +279,10 @@ gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace
     opt.item_rows = c->sched.item_rows;
     opt.join_part_keys = c->sched.join_part_keys;
     opt.workers = (uint32_t)c->n_cu * c->sched.wgs_per_cu;
-    CompiledBatch cb;
+    CompiledBatch& cb = c->cb;
+    const auto tc0 = std::chrono::steady_clock::now();
     compile_batch(reqs, n, opt, cb);
+    c->last_compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc0).count();
     gace_status first = GACE_OK;
     for (uint32_t i = 0; i < n; ++i) {
         if (per_req) per_req[i] = cb.status[i];
@@ -544,6 +546,7 @@ gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out) {
     out->join_ms = ctx->last_join_ms;
     out->scan_alg_bytes = ctx->last_scan_bytes;
     out->join_alg_bytes = ctx->last_join_bytes;
+    out->compile_ms = (float)ctx->last_compile_ms;
     return GACE_OK;
 }
 
@@ -625,8 +628,10 @@ gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, c
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "device properties");
     // schedules are only valid for the kernels they were timed on
+    // and for the launch mode they were timed in (graph replay or direct
+    // launches: the two overlap the scan and join kernels differently)
     const std::string prefix = std::string(prop.gcnArchName) + ":" + std::to_string(ctx->n_cu) + ":" +
-                               GACE_SOURCE_HASH + ":";
+                               GACE_SOURCE_HASH + ":" + (ctx->use_graph ? "graph" : "direct") + ":";
     const std::string bucket = shape_bucket(reqs, n);
     load_cache(ctx, cache_path, prefix);
     auto hit = ctx->tuned.find(bucket);
@@ -640,7 +645,7 @@ gace_status gace_autotune(gace_ctx* ctx, const gace_request* reqs, uint32_t n, c
         double t = 1e30;
         for (int rep = 0; rep < 4; ++rep) {
             auto t0 = std::chrono::steady_clock::now();
-            gace_status st = run_requests(ctx, reqs, n, per.data(), (hipStream_t)stream, true);
+            gace_status st = run_requests(ctx, reqs, n, per.data(), (hipStream_t)stream, ctx->use_graph);
             auto t1 = std::chrono::steady_clock::now();
             if (st != GACE_OK) return st;
             if (rep) t = std::min(t, std::chrono::duration<double, std::milli>(t1 - t0).count());

@@ -62,6 +62,8 @@ struct gace_ctx {
     uint64_t last_alg_bytes = 0, last_rows_preds = 0;
     bool last_timed = false;                      // last batch ran by direct launch with per-kernel events
     double last_scan_ms = 0.0, last_join_ms = 0.0;
+    double last_compile_ms = 0.0;                 // host validation + compilation of the last batch
+    gace::CompiledBatch cb;                       // the last batch's plan (buffers reused batch after batch)
     uint64_t last_scan_bytes = 0, last_join_bytes = 0;
     std::map<std::string, gace_schedule> tuned;   // shape bucket -> schedule
     // host-resident tables: copy stream, per-slot copy events, pinned staging
