@@ -104,38 +104,51 @@ static uint32_t join_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.joi
 static uint32_t agg_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.agg_wgs_per_cu; }
 
 // init kernel, then the scan kernel on st and the join kernel on the side
-// stream concurrently (they touch disjoint state), joined back into st
-static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, bool timed) {
+// stream concurrently (they touch disjoint state), joined back into st.
+// The kernels a batch has no items for are left out: a single selectivity
+// probe is init + scan on one stream.
+static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, bool timed, bool scans = true,
+                                 bool joins = true) {
     BatchArgsHost a = make_args(c);
     HIP_TRY(gace_launch_init(c->d_plan, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st), "init kernel");
-    HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
-    HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
-    if (timed) HIP_TRY(hipEventRecord(c->ev_j0, side), "event");
-    HIP_TRY(gace_launch_join(&a, join_grid(c), side), "join kernel");
-    HIP_TRY(gace_launch_agg(&a, agg_grid(c), side), "aggregation kernel");
-    if (timed) {
-        HIP_TRY(hipEventRecord(c->ev_j1, side), "event");
-        HIP_TRY(hipEventRecord(c->ev_s0, st), "event");
+    if (joins) {
+        HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
+        HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
+        if (timed) HIP_TRY(hipEventRecord(c->ev_j0, side), "event");
+        HIP_TRY(gace_launch_join(&a, join_grid(c), side), "join kernel");
+        HIP_TRY(gace_launch_agg(&a, agg_grid(c), side), "aggregation kernel");
+        if (timed) HIP_TRY(hipEventRecord(c->ev_j1, side), "event");
+    } else if (timed) {
+        HIP_TRY(hipEventRecord(c->ev_j0, st), "event");
+        HIP_TRY(hipEventRecord(c->ev_j1, st), "event");
     }
-    HIP_TRY(gace_launch_scan(&a, scan_grid(c), st), "scan kernel");
+    if (timed) HIP_TRY(hipEventRecord(c->ev_s0, st), "event");
+    if (scans) HIP_TRY(gace_launch_scan(&a, scan_grid(c), st), "scan kernel");
     if (timed) HIP_TRY(hipEventRecord(c->ev_s1, st), "event");
-    HIP_TRY(hipEventRecord(c->ev_join, side), "join event");
-    HIP_TRY(hipStreamWaitEvent(st, c->ev_join, 0), "join wait");
+    if (joins) {
+        HIP_TRY(hipEventRecord(c->ev_join, side), "join event");
+        HIP_TRY(hipStreamWaitEvent(st, c->ev_join, 0), "join wait");
+    }
     return GACE_OK;
 }
 
-static void drop_graph(gace_ctx* c) {
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
+static void drop_graph(gace_ctx* c, int k) {
+    if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->graph_exec[k] = nullptr;
+    c->graph[k] = nullptr;
 }
 
-static gace_status ensure_graph(gace_ctx* c) {
-    if (c->graph_exec && std::memcmp(&c->graph_sched, &c->sched, sizeof(gace_schedule)) == 0) return GACE_OK;
-    drop_graph(c);
+static void drop_graph(gace_ctx* c) {
+    for (int k = 0; k < 4; ++k) drop_graph(c, k);
+}
+
+// the graph of batch kind k ((has scans << 1) | has joins) for the current schedule
+static gace_status ensure_graph(gace_ctx* c, int k) {
+    if (c->graph_exec[k] && std::memcmp(&c->graph_sched[k], &c->sched, sizeof(gace_schedule)) == 0) return GACE_OK;
+    drop_graph(c, k);
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    gace_status st = launch_direct(c, c->cap_stream, c->cap_side, false);
+    gace_status st = launch_direct(c, c->cap_stream, c->cap_side, false, (k & 2) != 0, (k & 1) != 0);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (st != GACE_OK) {
@@ -143,9 +156,9 @@ static gace_status ensure_graph(gace_ctx* c) {
         return st;
     }
     if (e != hipSuccess) return hip_fail(e, "end capture");
-    c->graph = g;
-    HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0), "graph instantiate");
-    c->graph_sched = c->sched;
+    c->graph[k] = g;
+    HIP_TRY(hipGraphInstantiate(&c->graph_exec[k], g, nullptr, nullptr, 0), "graph instantiate");
+    c->graph_sched[k] = c->sched;
     return GACE_OK;
 }
 
@@ -173,10 +186,11 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
         HIP_TRY(hipMemcpyAsync(c->d_items, c->h_stage + kPlanCap, items_b, hipMemcpyHostToDevice, st), "item upload");
     HIP_TRY(hipEventRecord(c->ev0, st), "event");
     if (use_graph) {
-        if (gace_status s = ensure_graph(c)) return s;
-        HIP_TRY(hipGraphLaunch(c->graph_exec, st), "graph launch");
+        const int k = (cb.sel.empty() ? 0 : 2) | (cb.joins.empty() ? 0 : 1);
+        if (gace_status s = ensure_graph(c, k)) return s;
+        HIP_TRY(hipGraphLaunch(c->graph_exec[k], st), "graph launch");
     } else {
-        if (gace_status s = launch_direct(c, st, c->side_stream, true)) return s;
+        if (gace_status s = launch_direct(c, st, c->side_stream, true, !cb.sel.empty(), !cb.joins.empty())) return s;
     }
     c->last_timed = !use_graph;
     HIP_TRY(hipEventRecord(c->ev1, st), "event");

@@ -52,10 +52,11 @@ struct gace_ctx {
     bool use_graph = true;                        // batched path: replay the captured graph
     hipStream_t side_stream = nullptr;   // join kernel runs here, concurrently with the scan kernel
     gace_schedule sched{};
-    // graph of (init kernel, batch kernel) for the current schedule
-    hipGraphExec_t graph_exec = nullptr;
-    hipGraph_t graph = nullptr;
-    gace_schedule graph_sched{};
+    // captured launch graphs for the current schedule, one per batch kind:
+    // index (has scans << 1) | has joins
+    hipGraphExec_t graph_exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    gace_schedule graph_sched[4] = {};
     hipStream_t cap_stream = nullptr, cap_side = nullptr;
     // stats of the last batch
     double last_kernel_ms = 0.0;
