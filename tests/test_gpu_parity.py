@@ -412,6 +412,38 @@ def test_batch_repeatable_and_schedules_agree(g, torch_dev):
         g.gace_destroy(c)
 
 
+def test_batch_kinds_in_both_launch_modes(g, torch_dev):
+    """Batches of only selectivity requests, only joins, and both, each
+    replayed from its own captured graph and launched directly: every result
+    equals the plain path's, replay after replay."""
+    w = datagen.config4(scale=0.002, n_sel=30, n_join=4, seed_offset=41)
+    tabs, keys = _materialise(w, torch_dev)
+    c = g.gace_create(0, 2 << 30)
+    try:
+        def res(q):
+            return q.result() if isinstance(q, g.JoinRequest) else (q.result()[0].tolist(), q.result()[1:])
+        base = {}
+        for kind, i in w.order:
+            q = _requests(g, w, tabs, keys)[w.order.index((kind, i))]
+            if kind == "sel":
+                cnt, n, k = g.gace_probe_selectivity(c, q.table, q.preds, q.seed, q.rate, q.block_rows)
+                base[(kind, i)] = (cnt.tolist(), (n, k))
+            else:
+                base[(kind, i)] = g.gace_join_freq(c, q.R, q.S)
+        for graph in (True, False, True):
+            g.gace_set_graph(c, graph)
+            for pick in ("sel", "join", None):
+                order = [o for o in w.order if pick is None or o[0] == pick]
+                all_reqs = _requests(g, w, tabs, keys)
+                reqs = [all_reqs[w.order.index(o)] for o in order]
+                for rep in range(2):
+                    g.gace_batch_run(c, reqs)
+                    for o, q in zip(order, reqs):
+                        assert res(q) == base[o], (graph, pick, rep, o)
+    finally:
+        g.gace_destroy(c)
+
+
 def test_batch_invalid_request_fails_alone(g, ctx, torch_dev):
     import torch
     cols = [torch.arange(10_000, dtype=torch.int32, device=torch_dev)]
