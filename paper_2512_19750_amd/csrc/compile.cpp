@@ -706,14 +706,22 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     // costliest first, so the tail of the queue is short items.
     std::vector<Item> scan_items;
     std::vector<double> item_cost;
+    // one request on blocks under 4096 rows, with more than one kept block per
+    // 4096 rows expected (thr_max / 2^32 > B / 4096): decided row by row in
+    // whole tiles, which read every row of the item
+    auto is_fine = [](const ScanDesc& S) {
+        return S.n_req == 1 && S.log2B < kZoneLog2 && S.thr_max > (1ull << (S.log2B + 20));
+    };
     // a small batch (a single probe, a short served batch) still gets about
-    // four items per worker, down to items of 4096 rows
+    // four items per worker, down to items of 4096 rows; the rows an item
+    // reads are its kept rows, or all its rows for the row-by-row scan
     uint32_t item_rows = opt.item_rows;
     if (opt.workers) {
-        double kept = 0.0;
+        double rows_read = 0.0;
         for (const ScanDesc& S : scans)
-            kept += (double)S.n_rows * (S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0);
-        const double cap = std::max(4096.0, kept / (4.0 * opt.workers));
+            rows_read += (double)S.n_rows *
+                         (is_fine(S) || S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0);
+        const double cap = std::max(4096.0, rows_read / (4.0 * opt.workers));
         if (cap < item_rows) item_rows = (uint32_t)cap;
     }
     for (uint32_t s = 0; s < scans.size(); ++s) {
@@ -729,11 +737,9 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         if (gpb < 1.0) gpb = 1.0;
         const uint32_t rows = std::max<uint32_t>(1024u, (uint32_t)((double)item_rows / gpb));
         if (S.thr_max == 0) continue;
-        // one request on blocks under 4096 rows, with more than one kept block per 4096 rows
-        // expected (thr_max / 2^32 > B / 4096): decided row by row in whole
-        // tiles, which read every row of the item, so items are sized by rows
-        // and cut on tile boundaries
-        S.fine = S.n_req == 1 && S.log2B < kZoneLog2 && S.thr_max > (1ull << (S.log2B + 20)) ? 1u : 0u;
+        // the row-by-row scan reads every row of its items: they are sized by
+        // rows and cut on tile boundaries
+        S.fine = is_fine(S) ? 1u : 0u;
         uint64_t bb;
         if (S.fine) {
             const uint64_t per_tile = kZoneRows >> S.log2B;
