@@ -1931,10 +1931,15 @@ __device__ __forceinline__ bool zterm_may(const ZTerm& t, const ZoneCol& c, uint
 }
 
 // bit z of skip: no predicate can hold on zone z.  One thread per zone; each
-// wave's 64 bits are written as two whole 32-bit words.
+// wave's 64 bits are written as two whole 32-bit words.  The number of set
+// bits is added to *n_skip (zeroed by the caller), one atomic per workgroup.
 __global__ void __launch_bounds__(kWG) gace_zone_prune_kernel(const ZoneCol* zc, const ZTerm* terms,
                                                               const uint32_t* pred_off, uint32_t n_preds,
-                                                              uint64_t n_zones, uint32_t* skip) {
+                                                              uint64_t n_zones, uint32_t* skip,
+                                                              unsigned long long* n_skip) {
+    __shared__ uint32_t s_n;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     const uint64_t z = (uint64_t)blockIdx.x * kWG + threadIdx.x;
     bool may = false;
     if (z < n_zones) {
@@ -1949,7 +1954,10 @@ __global__ void __launch_bounds__(kWG) gace_zone_prune_kernel(const ZoneCol* zc,
     if ((threadIdx.x & 63) == 0 && w0 * 32 < n_zones) {
         skip[w0] = (uint32_t)sk;
         if ((w0 + 1) * 32 < n_zones) skip[w0 + 1] = (uint32_t)(sk >> 32);
+        if (sk) atomicAdd(&s_n, (uint32_t)__popcll(sk));
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_n) atomicAdd(n_skip, (unsigned long long)s_n);
 }
 
 }  // namespace gace
@@ -1966,11 +1974,12 @@ hipError_t gace_launch_zone_build(const void* col, uint32_t dtype, uint64_t n_ro
 }
 
 hipError_t gace_launch_zone_prune(const void* zc, const void* terms, const uint32_t* pred_off, uint32_t n_preds,
-                                  uint64_t n_zones, uint32_t* skip, hipStream_t stream) {
+                                  uint64_t n_zones, uint32_t* skip, void* n_skip, hipStream_t stream) {
     const uint64_t grid = (n_zones + gace::kWG - 1) / gace::kWG;
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL(gace::gace_zone_prune_kernel, dim3((uint32_t)grid), dim3(gace::kWG), 0, stream,
-                       (const gace::ZoneCol*)zc, (const gace::ZTerm*)terms, pred_off, n_preds, n_zones, skip);
+                       (const gace::ZoneCol*)zc, (const gace::ZTerm*)terms, pred_off, n_preds, n_zones, skip,
+                       (unsigned long long*)n_skip);
     return hipGetLastError();
 }
 

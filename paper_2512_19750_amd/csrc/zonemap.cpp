@@ -12,7 +12,7 @@ extern "C" {
 hipError_t gace_launch_zone_build(const void* col, uint32_t dtype, uint64_t n_rows, void* zmin, void* zmax,
                                   hipStream_t stream);
 hipError_t gace_launch_zone_prune(const void* zc, const void* terms, const uint32_t* pred_off, uint32_t n_preds,
-                                  uint64_t n_zones, uint32_t* skip, hipStream_t stream);
+                                  uint64_t n_zones, uint32_t* skip, void* n_skip, hipStream_t stream);
 }
 
 using gace::set_error;
@@ -188,40 +188,52 @@ extern "C" gace_status gace_probe_selectivity_zm(gace_ctx* ctx, const gace_table
         return GACE_EINVAL;
     }
     const uint32_t np = preds->n_preds, nt = np ? preds->pred_off[np] : 0;
+    // device workspace: skip bits | skipped-zone counter | terms | pred_off;
+    // the counter, terms and offsets go up in one copy, the counter as zero
     const uint64_t skip_b = align256((zm->n_zones + 31) / 32 * 4);
+    const uint64_t cnt_b = 256;
     const uint64_t term_b = align256((uint64_t)std::max<uint32_t>(nt, 1) * sizeof(gace_term));
     const uint64_t off_b = align256(((uint64_t)np + 1) * 4);
-    const uint64_t need = skip_b + term_b + off_b;
+    const uint64_t up_b = cnt_b + term_b + off_b;
+    const uint64_t need = skip_b + up_b;
     if (need > ctx->arena_bytes) {
         set_error("workspace too small for the zone-skip map: need " + std::to_string(need) + " bytes");
         return GACE_ENOMEM;
     }
     ZTRY(hipSetDevice(ctx->device), "set device");
-    if (ctx->h_hp_bytes < need) {
+    // pinned host staging: 256 B for the counter's download, then the upload
+    const uint64_t h_need = 256 + up_b;
+    if (ctx->h_hp_bytes < h_need) {
         if (ctx->h_hp) (void)hipHostFree(ctx->h_hp);
         ctx->h_hp = nullptr;
         ctx->h_hp_bytes = 0;
-        ZTRY(hipHostMalloc((void**)&ctx->h_hp, need, hipHostMallocDefault), "pinned staging");
-        ctx->h_hp_bytes = need;
+        ZTRY(hipHostMalloc((void**)&ctx->h_hp, h_need, hipHostMallocDefault), "pinned staging");
+        ctx->h_hp_bytes = h_need;
     }
     hipStream_t st = (hipStream_t)stream;
     uint32_t* d_skip = (uint32_t*)ctx->d_arena_base;
-    uint8_t* d_terms = ctx->d_arena_base + skip_b;
+    uint8_t* d_cnt = ctx->d_arena_base + skip_b;
+    uint8_t* d_terms = d_cnt + cnt_b;
     uint32_t* d_off = (uint32_t*)(d_terms + term_b);
-    if (nt) std::memcpy(ctx->h_hp + skip_b, preds->terms, (uint64_t)nt * sizeof(gace_term));
-    if (np) std::memcpy(ctx->h_hp + skip_b + term_b, preds->pred_off, ((uint64_t)np + 1) * 4);
-    ZTRY(hipMemcpyAsync(d_terms, ctx->h_hp + skip_b, term_b + off_b, hipMemcpyHostToDevice, st), "term upload");
-    ZTRY(gace_launch_zone_prune(zm->d_mem + zm->zc_off, d_terms, d_off, np, zm->n_zones, d_skip, st),
+    uint64_t* h_cnt = (uint64_t*)ctx->h_hp;
+    uint8_t* h_up = ctx->h_hp + 256;
+    std::memset(h_up, 0, cnt_b);
+    if (nt) std::memcpy(h_up + cnt_b, preds->terms, (uint64_t)nt * sizeof(gace_term));
+    if (np) std::memcpy(h_up + cnt_b + term_b, preds->pred_off, ((uint64_t)np + 1) * 4);
+    ZTRY(hipMemcpyAsync(d_cnt, h_up, up_b, hipMemcpyHostToDevice, st), "term upload");
+    ZTRY(gace_launch_zone_prune(zm->d_mem + zm->zc_off, d_terms, d_off, np, zm->n_zones, d_skip, d_cnt, st),
          "zone prune kernel");
+    if (zones_skipped) ZTRY(hipMemcpyAsync(h_cnt, d_cnt, 8, hipMemcpyDeviceToHost, st), "skip count download");
 
     gace::CompileOptions opt;
     opt.item_rows = ctx->sched.item_rows;
     opt.join_part_keys = ctx->sched.join_part_keys;
     opt.workers = (uint32_t)ctx->n_cu * ctx->sched.wgs_per_cu;
-    gace::CompiledBatch cb;
+    gace::CompiledBatch& cb = ctx->cb;
     gace::compile_batch(&r, 1, opt, cb);
     if (cb.status[0] != GACE_OK) {
         set_error(cb.errors[0]);
+        (void)hipStreamSynchronize(st);
         return cb.status[0];
     }
     if (cb.scans.size() == 1) {
@@ -233,17 +245,12 @@ extern "C" gace_status gace_probe_selectivity_zm(gace_ctx* ctx, const gace_table
         cb.scans[0].zskip = sd->zskip;
         cb.scans[0].n_zones = sd->n_zones;
     }
+    // the batch's done event follows the count download on the same stream
     if (!cb.sel.empty()) {
         if (gace_status e = gace::run_compiled(ctx, cb, &r, nullptr, st, false)) return e;
-    }
-    if (zones_skipped) {
+    } else {
         ZTRY(hipStreamSynchronize(st), "synchronize");
-        std::vector<uint32_t> bits((zm->n_zones + 31) / 32);
-        if (!bits.empty())
-            ZTRY(hipMemcpy(bits.data(), d_skip, bits.size() * 4, hipMemcpyDeviceToHost), "skip map download");
-        uint64_t n = 0;
-        for (uint32_t w : bits) n += (uint64_t)__builtin_popcount(w);
-        *zones_skipped = n;
     }
+    if (zones_skipped) *zones_skipped = *h_cnt;
     return GACE_OK;
 }
