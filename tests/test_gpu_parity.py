@@ -215,6 +215,27 @@ def test_join_small_vs_oracle(g, ctx, torch_dev, case):
     assert got == want
 
 
+@pytest.mark.parametrize("shift,nr,ns,B,rate", [(0, 100_001, 30_001, 2, 0.5), (0, 100_001, 30_001, 4096, 1.0),
+                                                 (1, 100_001, 30_001, 4096, 1.0), (1, 100_000, 30_000, 64, 0.7),
+                                                 (0, 1, 3, 2, 1.0)])
+def test_join_key_alignment_and_odd_lengths(g, ctx, torch_dev, shift, nr, ns, B, rate):
+    """Key columns that are only 8-byte aligned (a view one element into a
+    tensor, which the ABI allows) and odd lengths, whose last row ends the
+    last block."""
+    import torch
+    rng = np.random.default_rng(nr + 7 * B + shift)
+    r = rng.integers(-3000, 3000, size=nr + shift, dtype=np.int64)
+    s = rng.integers(-3000, 3000, size=ns + shift, dtype=np.int64)
+    r[-1], s[-1] = 2999, 2999          # the last rows pair with each other
+    _say("join alignment", shift, nr, ns, B, rate)
+    kr_full = torch.from_numpy(r).to(torch_dev)
+    ks_full = torch.from_numpy(s).to(torch_dev)
+    kr, ks = kr_full[shift:], ks_full[shift:]
+    assert (kr.data_ptr() % 16 == 0) == (shift == 0)
+    got = _join(g, ctx, kr, ks, 5, 6, 41, 43, rate, rate, B, B)
+    assert got == oracle.join_freq(r[shift:], 5, 41, rate, B, s[shift:], 6, 43, rate, B)
+
+
 @pytest.mark.parametrize("cache", [256, 4096])
 def test_join_cache_settings_agree(g, torch_dev, cache):
     import torch
