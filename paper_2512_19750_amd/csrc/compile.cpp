@@ -254,9 +254,11 @@ static void build_group(const std::vector<BitRef>& bits, const gace_table* table
         Iv x;
     };
     std::vector<TermIv> tiv;
-    std::vector<u128> B;
+    // interval boundaries: every stored one is below END <= 2^64, so they
+    // sort and search as 64-bit integers
+    std::vector<uint64_t> B;
     std::vector<uint32_t> nterm(nb);
-    std::vector<uint8_t> acc, tacc;
+    std::vector<Iv> cur, nxt;
     for (uint32_t col : refcols) {
         const uint32_t dt = table->cols[col].dtype;
         const bool wide = dt == GACE_I64;
@@ -269,8 +271,8 @@ static void build_group(const std::vector<BitRef>& bits, const gace_table* table
                 if (bits[i].terms[t].col == col) {
                     term_intervals(dt, bits[i].terms[t], iv);
                     for (const Iv& x : iv) {
-                        if (x.a > 0) B.push_back(x.a);
-                        if (x.b < END) B.push_back(x.b);
+                        if (x.a > 0) B.push_back((uint64_t)x.a);
+                        if (x.b < END) B.push_back((uint64_t)x.b);
                         tiv.push_back({i, nterm[i], x});
                     }
                     ++nterm[i];
@@ -281,7 +283,7 @@ static void build_group(const std::vector<BitRef>& bits, const gace_table* table
         const uint32_t m = (uint32_t)B.size();
         auto idx = [&](u128 x) -> uint32_t {
             if (x >= END) return m + 1;
-            return (uint32_t)(std::upper_bound(B.begin(), B.end(), x) - B.begin());
+            return (uint32_t)(std::upper_bound(B.begin(), B.end(), (uint64_t)x) - B.begin());
         };
         // acceptance: bit set on interval j when all the bit's terms on this column hold there
         std::vector<uint64_t> mask(m + 1, 0);
@@ -300,27 +302,38 @@ static void build_group(const std::vector<BitRef>& bits, const gace_table* table
                 }
                 continue;
             }
-            acc.assign(m + 1, 1);
+            // several terms on this column: intersect their sorted, disjoint
+            // interval lists (a term with no interval empties the result),
+            // then mark the result like a single term's intervals
+            cur.clear();
+            bool first = true;
             for (size_t k = e0; k < e;) {
                 const uint32_t t = tiv[k].term;
-                tacc.assign(m + 2, 0);
-                for (; k < e && tiv[k].term == t; ++k) {
-                    tacc[idx(tiv[k].x.a)] ^= 1;
-                    tacc[idx(tiv[k].x.b)] ^= 1;
+                const size_t k0 = k;
+                while (k < e && tiv[k].term == t) ++k;
+                if (first) {
+                    for (size_t q = k0; q < k; ++q) cur.push_back(tiv[q].x);
+                    first = false;
+                    continue;
                 }
-                uint8_t run = 0;
-                for (uint32_t j = 0; j <= m; ++j) {
-                    run ^= tacc[j];
-                    acc[j] &= run;
+                nxt.clear();
+                size_t a = 0, q = k0;
+                while (a < cur.size() && q < k) {
+                    const u128 lo = std::max(cur[a].a, tiv[q].x.a), hi = std::min(cur[a].b, tiv[q].x.b);
+                    if (lo < hi) nxt.push_back({lo, hi});
+                    if (cur[a].b < tiv[q].x.b) ++a; else ++q;
                 }
+                cur.swap(nxt);
             }
             // a term with no interval on the line (an empty range) accepts nothing
             uint32_t seen_terms = 0;
             for (size_t k = e0; k < e; ++k)
                 if (k == e0 || tiv[k].term != tiv[k - 1].term) ++seen_terms;
-            if (seen_terms < nterm[i]) acc.assign(m + 1, 0);
-            for (uint32_t j = 0; j <= m; ++j)
-                if (acc[j]) mask[j] |= bit;
+            if (seen_terms < nterm[i]) cur.clear();
+            for (const Iv& x : cur) {
+                diff[idx(x.a)] ^= bit;
+                diff[idx(x.b)] ^= bit;
+            }
         }
         uint64_t run = 0;
         for (uint32_t j = 0; j <= m; ++j) {
@@ -339,7 +352,7 @@ static void build_group(const std::vector<BitRef>& bits, const gace_table* table
         cb.prog.xform = dt == GACE_I32 ? XF_I32 : (dt == GACE_F32 ? XF_F32 : XF_I64);
         cb.masks = std::move(mask);
         cb.bnd.resize(m);
-        for (uint32_t j = 0; j < m; ++j) cb.bnd[j] = (uint64_t)B[j];
+        for (uint32_t j = 0; j < m; ++j) cb.bnd[j] = B[j];
         builds.push_back(std::move(cb));
     }
 
@@ -365,6 +378,7 @@ static void build_group(const std::vector<BitRef>& bits, const gace_table* table
     }
 
     std::vector<uint8_t> tab;
+    tab.reserve(total + 8 * (2 * builds.size() + 2));
     auto put = [&](const void* p, size_t n) -> uint32_t {
         const uint32_t off = align_up((uint32_t)tab.size(), 8);
         tab.resize(off + n);
