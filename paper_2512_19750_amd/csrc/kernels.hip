@@ -32,12 +32,16 @@ constexpr uint32_t kLdsCnt = kScanLdsGroups * 64 * 4;
 constexpr uint32_t kLdsHist = kScanLdsHist * 2 * 8;
 constexpr uint32_t kLdsThr = kScanLdsHist * 8 + 640;                             // thresholds + bit prefix sums
 constexpr uint32_t kLdsBytes = kLdsMisc + kLdsCnt + kLdsHist + kLdsThr + kGroupTabBudget;   // scan kernel
-constexpr int kPer = kTileKeys / kWG;                                              // staged keys per thread
-constexpr uint32_t kTileLdsBytes = 3 * 132 * 4 + kTileKeys * 12;                     // cursors, counts, starts, tile
+// partitioning tiles: kWG * KP keys, KP staged keys per thread (kTileKeys
+// or half of it; see gace_join_kernel)
+constexpr int kPerBig = kTileKeys / kWG;
+constexpr int kPerSmall = kTileKeys / 2 / kWG;
+constexpr uint32_t tile_lds_bytes(uint32_t keys) { return 3 * 132 * 4 + keys * 12; }   // cursors, counts, starts, tile
 constexpr uint32_t kBaseLdsBytes = ((1u << kPartBitsMax) + 1) * 4;                     // one side's partition starts
 constexpr uint32_t lds_max(uint32_t x, uint32_t y) { return x > y ? x : y; }
-constexpr uint32_t kJoinLdsBytes =
-    kLdsMisc + lds_max(kTileLdsBytes, lds_max(kBaseLdsBytes, (1u << kPartBitsMax) * 4));
+constexpr uint32_t join_lds_bytes(uint32_t keys) {
+    return kLdsMisc + lds_max(tile_lds_bytes(keys), lds_max(kBaseLdsBytes, (1u << kPartBitsMax) * 4));
+}
 
 // explicit address spaces: pointers read from the plan are generic to the
 // compiler; global loads through them must not become flat loads, which would
@@ -1016,7 +1020,7 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
 }
 
 // ---- LDS-staged partitioning
-// A tile of up to kTileKeys keys is counting-sorted by digit in LDS and each
+// A tile of up to kWG * KP keys is counting-sorted by digit in LDS and each
 // digit's run is written to its output cursor with consecutive lanes on
 // consecutive addresses, so the partition writes are whole cache lines
 // instead of one scattered 8-byte store per key.
@@ -1024,17 +1028,18 @@ struct TileLds {
     uint32_t* cur;               // [F] output cursor per digit (keys from the side's buffer start)
     uint32_t* cnt;               // [F] tile count per digit
     uint32_t* start;             // [F + 1] tile start per digit; start[F] = keys in the tile
-    unsigned long long* key;     // [kTileKeys] keys sorted by digit
-    uint32_t* dest;              // [kTileKeys] their output index
+    unsigned long long* key;     // [kWG * KP] keys sorted by digit
+    uint32_t* dest;              // [kWG * KP] their output index
 };
 
+template <int KP>
 __device__ __forceinline__ TileLds tile_lds(uint8_t* lds) {
     TileLds L;
     L.cur = (uint32_t*)(lds + kLdsMisc);
     L.cnt = L.cur + 132;
     L.start = L.cnt + 132;
     L.key = (unsigned long long*)(lds + kLdsMisc + 3 * 132 * 4);
-    L.dest = (uint32_t*)(L.key + kTileKeys);
+    L.dest = (uint32_t*)(L.key + (uint32_t)KP * kWG);
     return L;
 }
 
@@ -1045,12 +1050,12 @@ __device__ __forceinline__ TileLds tile_lds(uint8_t* lds) {
 // latencies overlap; each entry's output index is recorded beside it, so the
 // copy-out reads two independent LDS words per entry.
 // L.cnt must be zero on entry (it is again on return).
-template <bool kKeys>
-__device__ void tile_partition(uint64_t (&k)[kPer], uint32_t nt, uint32_t shift, uint32_t F,
+template <bool kKeys, int KP>
+__device__ void tile_partition(uint64_t (&k)[KP], uint32_t nt, uint32_t shift, uint32_t F,
                                GACE_GLOBAL int64_t* dst, const TileLds& L) {
-    uint32_t d[kPer], r[kPer];   // digit (~0: no entry at this position) and rank within it
+    uint32_t d[KP], r[KP];   // digit (~0: no entry at this position) and rank within it
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
+    for (int u = 0; u < KP; ++u) {
         const uint32_t pos = threadIdx.x + (uint32_t)u * kWG;
         const bool ok = pos < nt && (!kKeys || k[u] != kEmptyKey);
         if (kKeys) k[u] = mix_key(k[u]);
@@ -1058,7 +1063,7 @@ __device__ void tile_partition(uint64_t (&k)[kPer], uint32_t nt, uint32_t shift,
         d[u] = ok ? dg : ~0u;
     }
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) r[u] = d[u] != ~0u ? atomicAdd(&L.cnt[d[u]], 1u) : 0u;
+    for (int u = 0; u < KP; ++u) r[u] = d[u] != ~0u ? atomicAdd(&L.cnt[d[u]], 1u) : 0u;
     __syncthreads();
     if (threadIdx.x < 64) {
         const uint32_t lane = threadIdx.x;
@@ -1078,15 +1083,15 @@ __device__ void tile_partition(uint64_t (&k)[kPer], uint32_t nt, uint32_t shift,
     // all LDS reads of a step are issued before any dependent write, so their
     // latencies overlap (indices are clamped in range; writes stay guarded)
     {
-        uint32_t st[kPer], cu[kPer];
+        uint32_t st[KP], cu[KP];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
+        for (int u = 0; u < KP; ++u) {
             const uint32_t dd = d[u] != ~0u ? d[u] : 0u;
             st[u] = L.start[dd];
             cu[u] = L.cur[dd];
         }
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
+        for (int u = 0; u < KP; ++u) {
             if (d[u] != ~0u) {
                 const uint32_t at = st[u] + r[u];
                 L.key[at] = k[u];
@@ -1097,17 +1102,17 @@ __device__ void tile_partition(uint64_t (&k)[kPer], uint32_t nt, uint32_t shift,
     __syncthreads();
     {
         const uint32_t m = L.start[F];
-        uint32_t de[kPer];
-        unsigned long long kk[kPer];
+        uint32_t de[KP];
+        unsigned long long kk[KP];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
+        for (int u = 0; u < KP; ++u) {
             const uint32_t i = threadIdx.x + (uint32_t)u * kWG;
             const uint32_t ic = i < m ? i : 0u;
             de[u] = L.dest[ic];
             kk[u] = L.key[ic];
         }
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
+        for (int u = 0; u < KP; ++u) {
             const uint32_t i = threadIdx.x + (uint32_t)u * kWG;
             if (i < m) dst[de[u]] = (int64_t)kk[u];
         }
@@ -1124,8 +1129,9 @@ __device__ void tile_partition(uint64_t (&k)[kPer], uint32_t nt, uint32_t shift,
 // of one side: tile position t (thread + u * kWG) holds k[u] when t < nt.
 // Tiles run over the concatenated rows of the kept blocks of each 64-block
 // decision chunk, so small blocks still fill whole tiles.
-template <typename F>
+template <int KP, typename F>
 __device__ void for_each_tile(const JoinSide* D, uint64_t b0, uint64_t b1, uint8_t* lds, F&& f) {
+    constexpr uint64_t kTile = (uint64_t)KP * kWG;
     uint32_t* s_w0 = (uint32_t*)lds;
     unsigned long long* s_keep = (unsigned long long*)(lds + 256);
     uint32_t* s_kidx = (uint32_t*)(lds + 384);
@@ -1147,25 +1153,25 @@ __device__ void for_each_tile(const JoinSide* D, uint64_t b0, uint64_t b1, uint8
             // the next tile's keys are loaded while this tile is partitioned
             // positions past the end are clamped to the last one (loads stay
             // unconditional); the partitioner ignores them
-            auto load = [&](uint64_t t0, uint64_t (&k)[kPer]) {
+            auto load = [&](uint64_t t0, uint64_t (&k)[KP]) {
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) {
+                for (int u = 0; u < KP; ++u) {
                     uint64_t pos = t0 + threadIdx.x + (uint64_t)u * kWG;
                     pos = pos < total ? pos : total - 1;
                     const uint64_t row = ((cb + s_kidx[pos >> log2B]) << log2B) + (pos & (B - 1));
                     k[u] = (uint64_t)__builtin_nontemporal_load(keys + row);
                 }
             };
-            uint64_t k[kPer], kn[kPer];
+            uint64_t k[KP], kn[KP];
             load(0, k);
-            for (uint64_t t0 = 0; t0 < total; t0 += kTileKeys) {
-                const uint32_t nt = (uint32_t)min((uint64_t)kTileKeys, total - t0);
-                const bool more = t0 + kTileKeys < total;
-                if (more) load(t0 + kTileKeys, kn);
+            for (uint64_t t0 = 0; t0 < total; t0 += kTile) {
+                const uint32_t nt = (uint32_t)min((uint64_t)kTile, total - t0);
+                const bool more = t0 + kTile < total;
+                if (more) load(t0 + kTile, kn);
                 f(k, nt);
                 if (more) {
 #pragma unroll
-                    for (int u = 0; u < kPer; ++u) k[u] = kn[u];
+                    for (int u = 0; u < KP; ++u) k[u] = kn[u];
                 }
             }
         }
@@ -1177,6 +1183,7 @@ __device__ void for_each_tile(const JoinSide* D, uint64_t b0, uint64_t b1, uint8
 // hash bits) in the temporary buffer, or straight to their partition when one
 // pass suffices.  An item's run inside a bucket starts at the sum of its
 // offsets in the bucket's partitions, so both passes place keys in item order.
+template <int KP>
 __device__ void jscatter_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds) {
     JoinAcc& acc = a.accs[jd->acc];
     const uint32_t log2P = jd->log2P, P = 1u << log2P, log2P2 = jd->log2P2, log2P1 = log2P - log2P2;
@@ -1184,7 +1191,7 @@ __device__ void jscatter_item(const BatchArgs& a, const JoinDesc* jd, const Item
     const GACE_GLOBAL uint32_t* base =
         (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off) + (uint64_t)it.side * (P + 1);
     const GACE_GLOBAL uint32_t* row = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off) + (uint64_t)it.sub * P;
-    const TileLds L = tile_lds(lds);
+    const TileLds L = tile_lds<KP>(lds);
     for (uint32_t i = threadIdx.x; i < F1; i += kWG) {
         L.cur[i] = 0;
         L.cnt[i] = 0;
@@ -1198,21 +1205,23 @@ __device__ void jscatter_item(const BatchArgs& a, const JoinDesc* jd, const Item
     GACE_GLOBAL int64_t* dst = (GACE_GLOBAL int64_t*)(a.arena_base + (log2P2 ? acc.tmp_off : acc.buf_off)) +
                                (it.side ? acc.nkeys[0] : 0ull);
     const uint32_t shift = 64 - log2P1;
-    for_each_tile(&jd->side[it.side], it.begin, it.end, lds,
-                  [&](uint64_t (&k)[kPer], uint32_t nt) { tile_partition<true>(k, nt, shift, F1, dst, L); });
+    for_each_tile<KP>(&jd->side[it.side], it.begin, it.end, lds,
+                      [&](uint64_t (&k)[KP], uint32_t nt) { tile_partition<true, KP>(k, nt, shift, F1, dst, L); });
 }
 
 // second pass: a unit is one first-pass bucket of a group of consecutive
 // items of one side; its keys are contiguous in the temporary buffer and are
 // partitioned by the next log2P2 hash bits into their final partitions, where
 // the group's run starts at the first item's offsets
+template <int KP>
 __device__ void jscatter2_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds) {
+    constexpr uint64_t kTile = (uint64_t)KP * kWG;
     JoinAcc& acc = a.accs[jd->acc];
     const uint32_t log2P = jd->log2P, P = 1u << log2P, log2P2 = jd->log2P2, log2P1 = log2P - log2P2;
     const uint32_t F1 = 1u << log2P1, F2 = 1u << log2P2;
     const GACE_GLOBAL uint32_t* rows = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off);
     uint32_t* s_ctl = (uint32_t*)(lds + 352);
-    const TileLds L = tile_lds(lds);
+    const TileLds L = tile_lds<KP>(lds);
     if (__hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const uint32_t units0 = jd->n_groups[0] << log2P1;
     const uint32_t shift = 64 - log2P;
@@ -1259,23 +1268,23 @@ __device__ void jscatter2_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* 
         const uint64_t lo = (uint64_t)base[p0] + s_ctl[4] + s_ctl[6];
         const uint64_t hi = (uint64_t)base[p0] + s_ctl[5] + s_ctl[7];
         __syncthreads();
-        auto load = [&](uint64_t t0, uint64_t (&k)[kPer]) {
+        auto load = [&](uint64_t t0, uint64_t (&k)[KP]) {
 #pragma unroll
-            for (int u2 = 0; u2 < kPer; ++u2) {
+            for (int u2 = 0; u2 < KP; ++u2) {
                 const uint64_t pos = t0 + threadIdx.x + (uint64_t)u2 * kWG;
                 k[u2] = (uint64_t)__builtin_nontemporal_load(src + (pos < hi ? pos : hi - 1));
             }
         };
-        uint64_t k[kPer], kn[kPer];
+        uint64_t k[KP], kn[KP];
         if (lo < hi) load(lo, k);
-        for (uint64_t t0 = lo; t0 < hi; t0 += kTileKeys) {
-            const uint32_t nt = (uint32_t)min((uint64_t)kTileKeys, hi - t0);
-            const bool more = t0 + kTileKeys < hi;
-            if (more) load(t0 + kTileKeys, kn);
-            tile_partition<false>(k, nt, shift, F2, dst, L);
+        for (uint64_t t0 = lo; t0 < hi; t0 += kTile) {
+            const uint32_t nt = (uint32_t)min((uint64_t)kTile, hi - t0);
+            const bool more = t0 + kTile < hi;
+            if (more) load(t0 + kTile, kn);
+            tile_partition<false, KP>(k, nt, shift, F2, dst, L);
             if (more) {
 #pragma unroll
-                for (int u2 = 0; u2 < kPer; ++u2) k[u2] = kn[u2];
+                for (int u2 = 0; u2 < KP; ++u2) k[u2] = kn[u2];
             }
         }
     }
@@ -1706,7 +1715,12 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 8))
     }
 }
 
-// join phases (queue 1: items [n_scan_items, n_items), in phase order)
+// join phases (queue 1: items [n_scan_items, n_items), in phase order).
+// KP staged keys per thread in the partitioning tiles: kPerBig when the join
+// kernel has the GPU to itself; kPerSmall (143 instead of 226 VGPRs) when a
+// scan kernel runs beside it, so a CU that holds a scan workgroup still fits
+// two join waves per SIMD.
+template <int KP>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))) gace_join_kernel(BatchArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ uint32_t s_item;
@@ -1739,13 +1753,13 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))
             case IT_JSCATTER:
                 wait_count(&acc.base_done, 1);
                 t1 = (uint64_t)wall_clock64();
-                jscatter_item(a, jd, it, lds);
+                jscatter_item<KP>(a, jd, it, lds);
                 signal_count(&acc.scatter_done);
                 break;
             case IT_JSCATTER2:
                 wait_count(&acc.scatter_done, jd->n_items);
                 t1 = (uint64_t)wall_clock64();
-                jscatter2_item(a, jd, lds);
+                jscatter2_item<KP>(a, jd, lds);
                 signal_count(&acc.s2_done);
                 break;
             default:
@@ -2015,9 +2029,14 @@ hipError_t gace_launch_agg(const void* args, uint32_t grid, hipStream_t stream) 
     return hipGetLastError();
 }
 
-hipError_t gace_launch_join(const void* args, uint32_t grid, hipStream_t stream) {
+hipError_t gace_launch_join(const void* args, uint32_t grid, int beside_scan, hipStream_t stream) {
     const gace::BatchArgs& a = *(const gace::BatchArgs*)args;
-    hipLaunchKernelGGL(gace::gace_join_kernel, dim3(grid), dim3(gace::kWG), gace::kJoinLdsBytes, stream, a);
+    if (beside_scan)
+        hipLaunchKernelGGL(gace::gace_join_kernel<gace::kPerSmall>, dim3(grid), dim3(gace::kWG),
+                           gace::join_lds_bytes(gace::kPerSmall * gace::kWG), stream, a);
+    else
+        hipLaunchKernelGGL(gace::gace_join_kernel<gace::kPerBig>, dim3(grid), dim3(gace::kWG),
+                           gace::join_lds_bytes(gace::kPerBig * gace::kWG), stream, a);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ extern "C" {
 hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,
                             hipStream_t stream);
 hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream);
-hipError_t gace_launch_join(const void* args, uint32_t grid, hipStream_t stream);
+hipError_t gace_launch_join(const void* args, uint32_t grid, int beside_scan, hipStream_t stream);
 hipError_t gace_launch_agg(const void* args, uint32_t grid, hipStream_t stream);
 }
 
@@ -115,7 +115,9 @@ static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, 
         HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
         HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
         if (timed) HIP_TRY(hipEventRecord(c->ev_j0, side), "event");
-        HIP_TRY(gace_launch_join(&a, join_grid(c), side), "join kernel");
+        // the join kernel's smaller-tile variant leaves room on each CU for
+        // the scan kernel's workgroup
+        HIP_TRY(gace_launch_join(&a, join_grid(c), scans ? 1 : 0, side), "join kernel");
         HIP_TRY(gace_launch_agg(&a, agg_grid(c), side), "aggregation kernel");
         if (timed) HIP_TRY(hipEventRecord(c->ev_j1, side), "event");
     } else if (timed) {
