@@ -173,7 +173,7 @@ typedef struct {
 /* Launch schedule of the batched path (chosen by gace_autotune). */
 typedef struct {
     uint32_t wg_threads;       /* 256 or 512 */
-    uint32_t wgs_per_cu;       /* scan kernel grid = CUs * wgs_per_cu */
+    uint32_t wgs_per_cu;       /* scan kernel grid = CUs * wgs_per_cu (CUs * 1 in batches with joins) */
     uint32_t item_rows;        /* target sampled rows per work item */
     uint32_t count_mode;       /* 0 auto, 1 ballot, 2 transpose */
     uint32_t join_part_keys;   /* expected sampled keys per join hash partition (power of two) */

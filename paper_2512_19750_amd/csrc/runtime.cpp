@@ -99,7 +99,13 @@ static BatchArgsHost make_args(gace_ctx* c) {
     return a;
 }
 
-static uint32_t scan_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.wgs_per_cu; }
+// Beside the join kernel the scan gets one workgroup per CU: a CU then holds
+// it and two join workgroups (143 VGPRs each with the join kernel's small
+// tiles, 168 for the scan), and more scan workgroups would only take CUs from
+// the joins.  A batch without joins uses the tuned count.
+static uint32_t scan_grid(gace_ctx* c, bool joins) {
+    return (uint32_t)c->n_cu * (joins ? 1u : c->sched.wgs_per_cu);
+}
 static uint32_t join_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.join_wgs_per_cu; }
 static uint32_t agg_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.agg_wgs_per_cu; }
 
@@ -125,7 +131,7 @@ static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, 
         HIP_TRY(hipEventRecord(c->ev_j1, st), "event");
     }
     if (timed) HIP_TRY(hipEventRecord(c->ev_s0, st), "event");
-    if (scans) HIP_TRY(gace_launch_scan(&a, scan_grid(c), st), "scan kernel");
+    if (scans) HIP_TRY(gace_launch_scan(&a, scan_grid(c, joins), st), "scan kernel");
     if (timed) HIP_TRY(hipEventRecord(c->ev_s1, st), "event");
     if (joins) {
         HIP_TRY(hipEventRecord(c->ev_join, side), "join event");
