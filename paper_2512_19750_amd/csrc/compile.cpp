@@ -454,6 +454,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     out.jdesc.clear();
     out.n_counts = out.n_hist = 0;
     out.arena_static = 0;
+    out.est_scan_bytes = out.est_join_keys = 0.0;
     out.status.assign(n, GACE_OK);
     out.errors.assign(n, std::string());
 
@@ -642,6 +643,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
             side_p[sd] = D.thr >= kThrAll ? 1.0 : (double)D.thr / 4294967296.0;
             expect += (double)D.n * side_p[sd];
         }
+        out.est_join_keys += expect;
         uint32_t log2P = 0;
         while (log2P < kPartBitsMax && (double)(1u << log2P) * (double)opt.join_part_keys < expect) ++log2P;
         const uint32_t P = 1u << log2P;
@@ -768,6 +770,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
             Item it = {IT_SCAN, s, 0, 0, b, std::min(S.n_blocks, b + bb)};
             scan_items.push_back(it);
             item_cost.push_back((double)(it.end - it.begin) * (double)(1ull << S.log2B) * p * S.row_bytes * gpb);
+            out.est_scan_bytes += item_cost.back();
         }
     }
     {

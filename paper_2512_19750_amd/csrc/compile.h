@@ -50,6 +50,8 @@ struct CompiledBatch {
     std::vector<std::string> errors;
     uint32_t n_counts = 0, n_hist = 0;
     uint64_t arena_static = 0;       // joins' per-item tables at the start of the arena
+    double est_scan_bytes = 0.0;     // expected bytes the scans read (sum of the items' costs)
+    double est_join_keys = 0.0;      // expected sampled keys of the joins
 };
 
 // Validate every request; compile the valid ones.  Never throws.

@@ -99,12 +99,23 @@ static BatchArgsHost make_args(gace_ctx* c) {
     return a;
 }
 
-// Beside the join kernel the scan gets one workgroup per CU: a CU then holds
-// it and two join workgroups (143 VGPRs each with the join kernel's small
-// tiles, 168 for the scan), and more scan workgroups would only take CUs from
-// the joins.  A batch without joins uses the tuned count.
-static uint32_t scan_grid(gace_ctx* c, bool joins) {
-    return (uint32_t)c->n_cu * (joins ? 1u : c->sched.wgs_per_cu);
+// A large batch whose scans run beside its joins for much of the join stage.
+// Then the scan gets one workgroup per CU and the join kernel its small-tile
+// variant: a CU holds the scan workgroup (168 VGPRs) and two join workgroups
+// (143 each), and more scan workgroups would only take CUs from the joins.
+// Measured: the config-4 batch (scans reading an expected 14 B per sampled
+// join key, 1.7e9 keys) gains 1-2 % per step with direct launches and up to
+// 6 % with graph replay; served config-5 batches of a few requests, with the
+// same mix of work but ~5e7 join keys, lose 30 % of p50 latency.  So the
+// variant needs both: at least 6 B of scan per join key and 5e8 join keys.
+constexpr double kBesideBytesPerKey = 6.0;
+constexpr double kBesideMinKeys = 5e8;
+static bool scan_beside_joins(const CompiledBatch& cb) {
+    return !cb.sel.empty() && !cb.joins.empty() && cb.est_join_keys >= kBesideMinKeys &&
+           cb.est_scan_bytes >= kBesideBytesPerKey * cb.est_join_keys;
+}
+static uint32_t scan_grid(gace_ctx* c, bool beside) {
+    return (uint32_t)c->n_cu * (beside ? 1u : c->sched.wgs_per_cu);
 }
 static uint32_t join_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.join_wgs_per_cu; }
 static uint32_t agg_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.agg_wgs_per_cu; }
@@ -113,8 +124,8 @@ static uint32_t agg_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.agg_
 // stream concurrently (they touch disjoint state), joined back into st.
 // The kernels a batch has no items for are left out: a single selectivity
 // probe is init + scan on one stream.
-static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, bool timed, bool scans = true,
-                                 bool joins = true) {
+static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, bool timed, bool scans, bool joins,
+                                 bool beside) {
     BatchArgsHost a = make_args(c);
     HIP_TRY(gace_launch_init(c->d_plan, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st), "init kernel");
     if (joins) {
@@ -123,7 +134,7 @@ static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, 
         if (timed) HIP_TRY(hipEventRecord(c->ev_j0, side), "event");
         // the join kernel's smaller-tile variant leaves room on each CU for
         // the scan kernel's workgroup
-        HIP_TRY(gace_launch_join(&a, join_grid(c), scans ? 1 : 0, side), "join kernel");
+        HIP_TRY(gace_launch_join(&a, join_grid(c), beside ? 1 : 0, side), "join kernel");
         HIP_TRY(gace_launch_agg(&a, agg_grid(c), side), "aggregation kernel");
         if (timed) HIP_TRY(hipEventRecord(c->ev_j1, side), "event");
     } else if (timed) {
@@ -131,7 +142,7 @@ static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, 
         HIP_TRY(hipEventRecord(c->ev_j1, st), "event");
     }
     if (timed) HIP_TRY(hipEventRecord(c->ev_s0, st), "event");
-    if (scans) HIP_TRY(gace_launch_scan(&a, scan_grid(c, joins), st), "scan kernel");
+    if (scans) HIP_TRY(gace_launch_scan(&a, scan_grid(c, beside), st), "scan kernel");
     if (timed) HIP_TRY(hipEventRecord(c->ev_s1, st), "event");
     if (joins) {
         HIP_TRY(hipEventRecord(c->ev_join, side), "join event");
@@ -148,15 +159,16 @@ static void drop_graph(gace_ctx* c, int k) {
 }
 
 static void drop_graph(gace_ctx* c) {
-    for (int k = 0; k < 4; ++k) drop_graph(c, k);
+    for (int k = 0; k < 8; ++k) drop_graph(c, k);
 }
 
-// the graph of batch kind k ((has scans << 1) | has joins) for the current schedule
+// the graph of batch kind k ((scan beside the joins << 2) | (has scans << 1) | has joins) for the
+// current schedule
 static gace_status ensure_graph(gace_ctx* c, int k) {
     if (c->graph_exec[k] && std::memcmp(&c->graph_sched[k], &c->sched, sizeof(gace_schedule)) == 0) return GACE_OK;
     drop_graph(c, k);
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    gace_status st = launch_direct(c, c->cap_stream, c->cap_side, false, (k & 2) != 0, (k & 1) != 0);
+    gace_status st = launch_direct(c, c->cap_stream, c->cap_side, false, (k & 2) != 0, (k & 1) != 0, (k & 4) != 0);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (st != GACE_OK) {
@@ -193,12 +205,14 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     if (items_b)
         HIP_TRY(hipMemcpyAsync(c->d_items, c->h_stage + kPlanCap, items_b, hipMemcpyHostToDevice, st), "item upload");
     HIP_TRY(hipEventRecord(c->ev0, st), "event");
+    const bool beside = scan_beside_joins(cb);
     if (use_graph) {
-        const int k = (cb.sel.empty() ? 0 : 2) | (cb.joins.empty() ? 0 : 1);
+        const int k = (beside ? 4 : 0) | (cb.sel.empty() ? 0 : 2) | (cb.joins.empty() ? 0 : 1);
         if (gace_status s = ensure_graph(c, k)) return s;
         HIP_TRY(hipGraphLaunch(c->graph_exec[k], st), "graph launch");
     } else {
-        if (gace_status s = launch_direct(c, st, c->side_stream, true, !cb.sel.empty(), !cb.joins.empty())) return s;
+        if (gace_status s = launch_direct(c, st, c->side_stream, true, !cb.sel.empty(), !cb.joins.empty(), beside))
+            return s;
     }
     c->last_timed = !use_graph;
     HIP_TRY(hipEventRecord(c->ev1, st), "event");

@@ -54,9 +54,10 @@ struct gace_ctx {
     gace_schedule sched{};
     // captured launch graphs for the current schedule, one per batch kind:
     // index (has scans << 1) | has joins
-    hipGraphExec_t graph_exec[4] = {nullptr, nullptr, nullptr, nullptr};
-    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
-    gace_schedule graph_sched[4] = {};
+    // one graph per batch kind: (scan beside the joins << 2) | (has scans << 1) | has joins
+    hipGraphExec_t graph_exec[8] = {};
+    hipGraph_t graph[8] = {};
+    gace_schedule graph_sched[8] = {};
     hipStream_t cap_stream = nullptr, cap_side = nullptr;
     // stats of the last batch
     double last_kernel_ms = 0.0;
