@@ -376,6 +376,21 @@ def test_config4_full_batch_sampled(g, torch_dev):
         _say("config4 full batch")
         assert all(s == 0 for s in g.gace_batch_run(c, reqs))
         assert g.gace_last_kernel_stats(c)["timed"]
+        direct = [q.result() for q in reqs]
+        # the same batch replayed from its captured graph (the batched path's
+        # default launch; this batch takes the small-tile join kernel beside
+        # one scan workgroup per CU in both modes)
+        g.gace_set_graph(c, True)
+        _say("config4 full batch, graph replay")
+        for rep in range(2):
+            assert all(s == 0 for s in g.gace_batch_run(c, reqs))
+            for q, d in zip(reqs, direct):
+                r = q.result()
+                if isinstance(q, g.JoinRequest):
+                    assert r == d
+                else:
+                    assert r[0].tolist() == d[0].tolist() and r[1:] == d[1:]
+        g.gace_set_graph(c, False)
         for q in reqs:
             if isinstance(q, g.JoinRequest):
                 assert g.gace_join_freq(c, q.R, q.S) == q.result()
