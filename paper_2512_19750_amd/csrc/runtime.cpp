@@ -103,11 +103,12 @@ static BatchArgsHost make_args(gace_ctx* c) {
 // Then the scan gets one workgroup per CU and the join kernel its small-tile
 // variant: a CU holds the scan workgroup (168 VGPRs) and two join workgroups
 // (143 each), and more scan workgroups would only take CUs from the joins.
-// Measured: the config-4 batch (scans reading an expected 14 B per sampled
-// join key, 1.7e9 keys) gains 1-2 % per step with direct launches and up to
-// 6 % with graph replay; served config-5 batches of a few requests, with the
-// same mix of work but ~5e7 join keys, lose 30 % of p50 latency.  So the
-// variant needs both: at least 6 B of scan per join key and 5e8 join keys.
+// Measured: a batch of 448 selectivity and 64 join requests over 50 GB
+// (scans reading an expected 14 B per sampled join key, 1.7e9 keys) gains up
+// to 6 % per step with graph replay; a served stream of batches of a few
+// such requests (the same mix of work, ~5e7 join keys) loses 30 % of its p50
+// latency at 5000 requests/s.  So the variant needs both: at least 6 B of
+// scan per join key and 5e8 join keys.
 constexpr double kBesideBytesPerKey = 6.0;
 constexpr double kBesideMinKeys = 5e8;
 static bool scan_beside_joins(const CompiledBatch& cb) {
