@@ -42,7 +42,9 @@
  *                  predicates in one request)
  *   GACE_ENOMEM    the workspace is too small for the request (the message
  *                  states the bytes needed)
- *   GACE_EOVERFLOW a join whose n_R * n_S is >= 2^64 (bounds sum f_R f_S)
+ *   GACE_EOVERFLOW reserved, never returned: each join side is limited to
+ *                  2^32 - 1 keys (GACE_EINVAL beyond), so n_R * n_S, which
+ *                  bounds sum f_R f_S, stays below 2^64
  *   GACE_EDEVICE   a HIP runtime error (the message carries HIP's text)
  *   GACE_EBUSY     the server queue is full
  *   GACE_ETIMEOUT  gace_server_wait timed out; the request is still running
@@ -191,7 +193,7 @@ const char* gace_last_error(void);
 const char* gace_version(void);
 
 /* Validate a request on the host only (no device access, no context):
-   the checks listed under GACE_EINVAL / GACE_EOVERFLOW above. */
+   the checks listed under GACE_EINVAL above. */
 gace_status gace_check_request(const gace_request* req);
 
 /* ---------------------------------------------------------------- plain path */
@@ -258,6 +260,17 @@ gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out);
    default) or direct launches with per-kernel timing events.  Results are
    identical. */
 gace_status gace_set_graph(gace_ctx* ctx, int enable);
+
+/* Bound on a join's phase waits on the device.  Each join phase waits for
+   the join's items of the phase before it, all queued ahead of it (and a
+   merge of a split partition for that partition's chunks), so the waits
+   always end; as a guard each gives up after `polls` polls of its counter,
+   and the join then fails with GACE_EDEVICE instead of hanging the kernel.
+   0 makes every such wait give up at once (this is how the failure path is
+   tested from the host; every kernel still exits normally).  Default 2^24
+   polls, many seconds.  The other requests of the batch are unaffected.
+   Errors: GACE_EINVAL (NULL context). */
+gace_status gace_set_spin_limit(gace_ctx* ctx, uint64_t polls);
 
 /* Per-item device trace of the last batch (for profiling the batched path).
    Item kinds: 1 scan, 2 join histogram, 3 join offsets, 4 join partition

@@ -169,7 +169,7 @@ ABI_FUNCTIONS = [
     "gace_create", "gace_destroy", "gace_last_error", "gace_version", "gace_check_request",
     "gace_probe_selectivity", "gace_join_freq", "gace_batch_run", "gace_autotune", "gace_get_schedule",
     "gace_set_schedule", "gace_last_batch_stats", "gace_last_kernel_stats", "gace_set_graph",
-    "gace_set_trace", "gace_get_trace",
+    "gace_set_trace", "gace_get_trace", "gace_set_spin_limit",
     "gace_server_create", "gace_server_submit",
     "gace_server_wait", "gace_server_wait_times", "gace_server_stats_get", "gace_server_destroy",
     # gace_gate.h
@@ -223,6 +223,7 @@ def lib():
             "gace_last_kernel_stats": ([P, ctypes.POINTER(gace_kernel_stats)], i32),
             "gace_set_graph": ([P, ctypes.c_int], i32),
             "gace_set_trace": ([P, ctypes.c_int], i32),
+            "gace_set_spin_limit": ([P, u64], i32),
             "gace_get_trace": ([P, ctypes.POINTER(gace_trace_rec), u32, ctypes.POINTER(u32),
                                 ctypes.POINTER(ctypes.c_double)], i32),
             "gace_server_create": ([ctypes.c_int, ctypes.POINTER(gace_server_cfg), ctypes.POINTER(P)], i32),
@@ -539,6 +540,10 @@ def gace_last_kernel_stats(ctx: int) -> dict:
 
 def gace_set_graph(ctx: int, enable: bool = True):
     _check(lib().gace_set_graph(ctx, 1 if enable else 0))
+
+
+def gace_set_spin_limit(ctx: int, polls: int):
+    _check(lib().gace_set_spin_limit(ctx, int(polls)))
 
 
 def gace_set_trace(ctx: int, enable: bool = True):

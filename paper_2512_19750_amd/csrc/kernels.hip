@@ -65,6 +65,7 @@ struct BatchArgs {
     uint32_t count_mode;       // 0 auto, 1 ballot, 2 transpose
     uint32_t agg_slots;        // aggregation kernel: LDS table slots (power of two)
     TraceRec* trace;           // one record per item when the plan asks for tracing
+    uint64_t spin_limit;       // polls before a join's phase wait gives up (0: at once)
 };
 
 // hardware register XCC_ID (s_getreg: id 20, offset 0, 4 bits): which XCD runs this wave
@@ -83,6 +84,17 @@ __device__ __forceinline__ void trace_item(const BatchArgs& a, const PlanHdr& H,
     r.t_end = (uint64_t)wall_clock64();
     r.work = work;
     a.trace[idx] = r;
+}
+
+// Thread 0 polls *p until it reaches target, at most `limit` times (0: it
+// gives up at once); true when the target was reached.
+__device__ __forceinline__ bool poll_count(const uint32_t* p, uint32_t target, uint64_t limit) {
+    if (limit == 0) return false;
+    for (uint64_t polls = 1; __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target; ++polls) {
+        if (polls >= limit) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
 }
 
 // ------------------------------------------------------------------ sampler
@@ -1557,7 +1569,7 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
     JoinAcc& acc = a.accs[jd->acc];
     const uint32_t P = 1u << jd->log2P;
     unsigned long long* s_red = (unsigned long long*)(lds + 320);
-    uint32_t* s_ctl = (uint32_t*)(lds + 352);   // [0] claims [1] over [2] unit [3] sp [4] m [5] r [6] emitted
+    uint32_t* s_ctl = (uint32_t*)(lds + 352);   // [0] claims [1] over [2] unit [3] sp [4] m [5] r [6] emitted [7] merge ready
     AggLds T;
     const uint32_t cap = a.agg_slots;
     T.key = (unsigned long long*)(lds + kLdsMisc);
@@ -1596,12 +1608,20 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
         const uint64_t bR = base0[p], nR = base0[p + 1] - bR, bS = base1[p], nS = base1[p + 1] - bS;
         if (U.kind == AU_MERGE) {
             // wait until every chunk of this partition has emitted its table
+            // (bounded like the phase waits: giving up fails the join)
             if (threadIdx.x == 0) {
-                while (__hip_atomic_load(&done[U.ord], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < U.b)
-                    __builtin_amdgcn_s_sleep(2);
+                const bool ok = poll_count(&done[U.ord], U.b, a.spin_limit);
+                if (!ok) atomicMax(&acc.status, 4ull);
+                s_ctl[7] = ok ? 1u : 0u;
             }
             __syncthreads();
             __threadfence();
+            if (!s_ctl[7]) {
+                ++n_taken;
+                if (threadIdx.x == 0) s_ctl[2] = claim_next;
+                __syncthreads();
+                continue;
+            }
             agg_size(T, (uint64_t)a.agg_slots, a.agg_slots);
             aggregate(
                 T,
@@ -1673,13 +1693,20 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
 }
 
 // ------------------------------------------------------------------ kernels
-__device__ __forceinline__ void wait_count(uint32_t* p, uint32_t target) {
+// Waits for a join phase counter, bounded: a wait that gives up marks the
+// join failed (status 4, reported to the host as a device error) and returns
+// false, so a lost signal ends the kernel instead of hanging it.  A join
+// whose status is already set skips its remaining phases the same way.
+__device__ __forceinline__ bool wait_count(const BatchArgs& a, uint32_t* p, uint32_t target, JoinAcc& acc,
+                                           uint32_t* s_flag) {
     if (threadIdx.x == 0) {
-        while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target)
-            __builtin_amdgcn_s_sleep(2);
+        const bool ok = poll_count(p, target, a.spin_limit);
+        if (!ok) atomicMax(&acc.status, 4ull);
+        *s_flag = ok && __hip_atomic_load(&acc.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 ? 1u : 0u;
     }
     __syncthreads();
     __threadfence();
+    return *s_flag != 0;
 }
 
 __device__ __forceinline__ void signal_count(uint32_t* p) {
@@ -1723,7 +1750,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 8))
 template <int KP>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))) gace_join_kernel(BatchArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    __shared__ uint32_t s_item;
+    __shared__ uint32_t s_item, s_flag;
     const PlanHdr H = *(const PlanHdr*)a.plan;
     for (;;) {
         const uint32_t idx = pop_item(&a.head[1], H.n_scan_items, &s_item);
@@ -1739,27 +1766,31 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))
                 signal_count(&acc.hist_done);
                 break;
             case IT_JOFF:
-                wait_count(&acc.hist_done, jd->n_items);
-                t1 = (uint64_t)wall_clock64();
-                joff_item(a, jd, it, lds);
+                if (wait_count(a, &acc.hist_done, jd->n_items, acc, &s_flag)) {
+                    t1 = (uint64_t)wall_clock64();
+                    joff_item(a, jd, it, lds);
+                }
                 signal_count(&acc.off_done);
                 break;
             case IT_JBASE:
-                wait_count(&acc.off_done, jd->n_off);
-                t1 = (uint64_t)wall_clock64();
-                jbase_item(a, jd, lds);
+                if (wait_count(a, &acc.off_done, jd->n_off, acc, &s_flag)) {
+                    t1 = (uint64_t)wall_clock64();
+                    jbase_item(a, jd, lds);
+                }
                 signal_count(&acc.base_done);
                 break;
             case IT_JSCATTER:
-                wait_count(&acc.base_done, 1);
-                t1 = (uint64_t)wall_clock64();
-                jscatter_item<KP>(a, jd, it, lds);
+                if (wait_count(a, &acc.base_done, 1, acc, &s_flag)) {
+                    t1 = (uint64_t)wall_clock64();
+                    jscatter_item<KP>(a, jd, it, lds);
+                }
                 signal_count(&acc.scatter_done);
                 break;
             case IT_JSCATTER2:
-                wait_count(&acc.scatter_done, jd->n_items);
-                t1 = (uint64_t)wall_clock64();
-                jscatter2_item<KP>(a, jd, lds);
+                if (wait_count(a, &acc.scatter_done, jd->n_items, acc, &s_flag)) {
+                    t1 = (uint64_t)wall_clock64();
+                    jscatter2_item<KP>(a, jd, lds);
+                }
                 signal_count(&acc.s2_done);
                 break;
             default:

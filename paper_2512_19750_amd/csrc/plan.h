@@ -156,7 +156,7 @@ struct JoinAcc {
     unsigned long long join, ndv[2], n[2], sent[2];
     unsigned long long buf_off;             // arena offset of the partitioned keys (R then S)
     unsigned long long nkeys[2];            // sampled keys per side other than the sentinel value
-    unsigned long long status;              // 0 ok, 2 arena exhausted, 3 aggregation stack overflow
+    unsigned long long status;              // 0 ok, 2 arena exhausted, 3 aggregation stack overflow, 4 a wait gave up
     unsigned long long merge_off;           // arena offset of the chunk tables (kChunkKeys entries per slot)
     unsigned long long tmp_off;             // arena offset of the first-pass buffer (two-pass partitioning)
     uint32_t next_unit, n_units;

@@ -39,6 +39,7 @@ struct BatchArgsHost {
     uint32_t count_mode;
     uint32_t agg_slots;
     TraceRec* trace;
+    uint64_t spin_limit;
 };
 
 static thread_local std::string g_err;
@@ -96,6 +97,7 @@ static BatchArgsHost make_args(gace_ctx* c) {
     a.count_mode = c->sched.count_mode;
     a.agg_slots = agg_slots(c->sched);
     a.trace = c->d_trace;
+    a.spin_limit = c->spin_limit;
     return a;
 }
 
@@ -278,6 +280,9 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
         if (A.status == 2) {
             set_error("workspace arena too small for the partitioned join keys of this batch");
             s = GACE_ENOMEM;
+        } else if (A.status == 4) {
+            set_error("a join phase wait on the device gave up before its dependency finished");
+            s = GACE_EDEVICE;
         } else if (A.status != 0) {
             set_error("join aggregation could not split a partition further");
             s = GACE_EDEVICE;
@@ -305,9 +310,19 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
 
 gace_status run_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
                          hipStream_t st, bool use_graph) {
-    if (gace_status s = launch_compiled(c, cb, st, use_graph)) return s;
-    HIP_TRY(hipEventSynchronize(c->ev_done), "synchronize");
-    return finish_compiled(c, cb, reqs, per_req);
+    gace_status s = launch_compiled(c, cb, st, use_graph);
+    if (s == GACE_OK) {
+        const hipError_t e = hipEventSynchronize(c->ev_done);
+        if (e == hipSuccess) return finish_compiled(c, cb, reqs, per_req);
+        s = hip_fail(e, "synchronize");
+    }
+    // nothing came back: every request that passed validation fails with the
+    // launch's status and its outputs stay untouched
+    if (per_req) {
+        for (const SelOut& o : cb.sel) per_req[o.req] = s;
+        for (const JoinOut& o : cb.joins) per_req[o.req] = s;
+    }
+    return s;
 }
 
 gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace_status* per_req, hipStream_t st,
@@ -584,6 +599,16 @@ gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out) {
     out->scan_alg_bytes = ctx->last_scan_bytes;
     out->join_alg_bytes = ctx->last_join_bytes;
     out->compile_ms = (float)ctx->last_compile_ms;
+    return GACE_OK;
+}
+
+gace_status gace_set_spin_limit(gace_ctx* ctx, uint64_t polls) {
+    if (!ctx) {
+        set_error("NULL context");
+        return GACE_EINVAL;
+    }
+    ctx->spin_limit = polls;
+    drop_graph(ctx);   // the limit is a kernel argument captured in the graphs
     return GACE_OK;
 }
 

@@ -52,9 +52,7 @@ struct gace_ctx {
     bool use_graph = true;                        // batched path: replay the captured graph
     hipStream_t side_stream = nullptr;   // join kernel runs here, concurrently with the scan kernel
     gace_schedule sched{};
-    // captured launch graphs for the current schedule, one per batch kind:
-    // index (has scans << 1) | has joins
-    // one graph per batch kind: (scan beside the joins << 2) | (has scans << 1) | has joins
+    // captured launch graphs for the current schedule, one per batch kind: (scan beside the joins << 2) | (has scans << 1) | has joins
     hipGraphExec_t graph_exec[8] = {};
     hipGraph_t graph[8] = {};
     gace_schedule graph_sched[8] = {};
@@ -73,6 +71,7 @@ struct gace_ctx {
     hipEvent_t ev_h0[2] = {nullptr, nullptr}, ev_h1[2] = {nullptr, nullptr}, ev_d2h = nullptr;
     uint8_t* h_hp = nullptr;
     uint64_t h_hp_bytes = 0;
+    uint64_t spin_limit = 1ull << 24;             // polls before a join phase wait on the device gives up
     bool trace = false;                           // record per-item device timestamps
     std::vector<TraceRec> last_trace;
     double ticks_per_us = 0.0;
