@@ -211,6 +211,24 @@ gace_status gace_probe_selectivity(gace_ctx* ctx, const gace_table* table, const
 gace_status gace_join_freq(gace_ctx* ctx, const gace_keys* R, const gace_keys* S, gace_join_result* out,
                            void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   probe as gace_probe_selectivity, with the same results, on the calling
+   thread's current HIP device and without a context.  Its device scratch is
+   a static array of the library (about 4 MiB per GPU the process runs on,
+   held until the process ends): a plan of at most 2 MiB, at most 32,768
+   work items and 131,072 counters; larger requests fail with GACE_ENOMEM
+   before any device work and leave counts untouched.  It calls no hipMalloc,
+   hipHostMalloc or hipFree (the host compiles into reused per-thread
+   buffers).  All calls on one GPU share that GPU's scratch: calls that
+   overlap on one GPU, from several threads or on several streams, race.
+   Returns once the results are in counts / info (host memory).  Errors as
+   gace_probe_selectivity, plus GACE_EDEVICE if the scratch's device address
+   cannot be found. */
+gace_status gace_probe_selectivity_noalloc(const gace_table* table, const gace_predicates* preds,
+                                           const gace_sample_spec* spec, uint64_t* counts, gace_probe_info* info,
+                                           void* stream);
+
 /* ---------------------------------------------------------------- batched path */
 /* Run n requests of either kind in one persistent, graph-replayed launch.
    Selectivity requests on the same table, seed and block size share one

@@ -185,6 +185,7 @@ ABI_FUNCTIONS = [
     # gace_zone.h
     "gace_zonemap_build", "gace_zonemap_destroy", "gace_zonemap_info", "gace_zonemap_read",
     "gace_probe_selectivity_zm",
+    "gace_probe_selectivity_noalloc",
 ]
 
 _lib = None
@@ -212,6 +213,9 @@ def lib():
             "gace_probe_selectivity": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
                                         ctypes.POINTER(gace_sample_spec), ctypes.POINTER(ctypes.c_uint64),
                                         ctypes.POINTER(gace_probe_info), P], i32),
+            "gace_probe_selectivity_noalloc": ([ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
+                                                ctypes.POINTER(gace_sample_spec), ctypes.POINTER(ctypes.c_uint64),
+                                                ctypes.POINTER(gace_probe_info), P], i32),
             "gace_join_freq": ([P, ctypes.POINTER(gace_keys), ctypes.POINTER(gace_keys),
                                 ctypes.POINTER(gace_join_result), P], i32),
             "gace_batch_run": ([P, ctypes.POINTER(gace_request), u32, ctypes.POINTER(i32), P], i32),
@@ -478,6 +482,25 @@ def gace_probe_selectivity(ctx: int, table: Table, preds, seed: int = 0, rate: f
     _check(lib().gace_probe_selectivity(ctx, ctypes.byref(t), ctypes.byref(p), ctypes.byref(s),
                                         counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                         ctypes.byref(info), _stream_handle(stream)))
+    return counts[:len(preds)], int(info.sampled_rows), int(info.kept_blocks)
+
+
+def gace_probe_selectivity_noalloc(table: Table, preds, seed: int = 0, rate: float = 1.0,
+                                   block_rows: int = 4096, stream=None, counts=None):
+    """As gace_probe_selectivity, on the current device, with the library's
+    static scratch and no context.  counts: an optional uint64 host array of
+    len(preds) entries to write into.  -> (counts, sampled_rows, kept_blocks)"""
+    keep = _Keep()
+    t = _make_table(table, keep)
+    p = _make_preds(preds, [_dtype_code(c) for c in table.cols], keep)
+    s = _make_spec(seed, rate, block_rows)
+    if counts is None:
+        counts = np.zeros(max(len(preds), 1), dtype=np.uint64)
+    assert counts.dtype == np.uint64 and counts.flags.c_contiguous and len(counts) >= len(preds)
+    info = gace_probe_info()
+    _check(lib().gace_probe_selectivity_noalloc(ctypes.byref(t), ctypes.byref(p), ctypes.byref(s),
+                                                counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                                ctypes.byref(info), _stream_handle(stream)))
     return counts[:len(preds)], int(info.sampled_rows), int(info.kept_blocks)
 
 

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgace.so")
-SOURCES = ["csrc/kernels.hip", "csrc/compile.cpp", "csrc/runtime.cpp", "csrc/server.cpp", "csrc/gate.cpp", "csrc/hostpath.cpp", "csrc/estimate.cpp", "csrc/zonemap.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/compile.cpp", "csrc/runtime.cpp", "csrc/server.cpp", "csrc/gate.cpp", "csrc/hostpath.cpp", "csrc/estimate.cpp", "csrc/zonemap.cpp",
+           "csrc/noalloc.hip"]
 HIPCC = "/opt/rocm/bin/hipcc"
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-shared", "-std=c++17", "-Wall",
          # packed fp32 instructions stay disabled in all device code

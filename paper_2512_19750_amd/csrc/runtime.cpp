@@ -16,31 +16,7 @@
 #define GACE_SOURCE_HASH "unversioned"
 #endif
 
-extern "C" {
-hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,
-                            hipStream_t stream);
-hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream);
-hipError_t gace_launch_join(const void* args, uint32_t grid, int beside_scan, hipStream_t stream);
-hipError_t gace_launch_agg(const void* args, uint32_t grid, hipStream_t stream);
-}
-
 namespace gace {
-
-// kernel argument block (must match kernels.hip)
-struct BatchArgsHost {
-    const uint8_t* plan;
-    const Item* items;
-    uint32_t* head;
-    unsigned long long* counts;
-    unsigned long long* hist;
-    JoinAcc* accs;
-    uint8_t* arena_base;
-    Arena* arena;
-    uint32_t count_mode;
-    uint32_t agg_slots;
-    TraceRec* trace;
-    uint64_t spin_limit;
-};
 
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
@@ -56,7 +32,7 @@ static gace_status hip_fail(hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
-static gace_schedule default_schedule() {
+gace_schedule default_schedule() {
     gace_schedule s;
     std::memset(&s, 0, sizeof(s));
     s.wg_threads = 256;

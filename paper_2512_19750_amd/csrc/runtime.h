@@ -23,7 +23,35 @@ constexpr uint64_t kMiscCap = 4096;
 constexpr uint64_t kTraceCap = (kItemsCap / sizeof(Item)) * sizeof(TraceRec);
 constexpr uint64_t kFixedBytes = kPlanCap + kItemsCap + kCountsCap + kHistCap + kAccsCap + kMiscCap + kTraceCap;
 
+// kernel argument block (must match kernels.hip)
+struct BatchArgsHost {
+    const uint8_t* plan;
+    const Item* items;
+    uint32_t* head;
+    unsigned long long* counts;
+    unsigned long long* hist;
+    JoinAcc* accs;
+    uint8_t* arena_base;
+    Arena* arena;
+    uint32_t count_mode;
+    uint32_t agg_slots;
+    TraceRec* trace;
+    uint64_t spin_limit;
+};
+
+gace_schedule default_schedule();
+
 }  // namespace gace
+
+// kernel launchers (kernels.hip; internal, not part of the public ABI)
+extern "C" {
+hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,
+                            hipStream_t stream);
+hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream);
+hipError_t gace_launch_join(const void* args, uint32_t grid, int beside_scan, hipStream_t stream);
+hipError_t gace_launch_agg(const void* args, uint32_t grid, hipStream_t stream);
+}
+
 
 using gace::TraceRec;
 
