@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+JOIN_FIELDS = ["join_card", "ndv_R", "ndv_S", "n_R", "n_S", "f1_R", "f1_S", "f2_R", "f2_S"]
 CSRC = os.path.join(ROOT, "paper_2512_19750_amd", "csrc")
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("kernels.hip", "plan.h", "compile.cpp")]
 
@@ -42,27 +43,88 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counters_path(kernel: str) -> str:
-    return os.path.join(ROOT, "profiles", "%s_c4_counters.md" % kernel)
+def counters_path(kernel: str, workload: str = "c4") -> str:
+    return os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, workload))
 
 
-def stored_traffic(kernel: str):
+def stored_counters(kernel: str, workload: str = "c4") -> dict:
+    """Figures per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (`name: value` lines), if it was taken on the
+    current kernel sources (else {})."""
+    path = counters_path(kernel, workload)
+    if not os.path.exists(path):
+        return {}
+    out = {}
+    for line in open(path).read().splitlines():
+        if ":" not in line or line.startswith(("|", "#", " ")):
+            continue
+        k, v = line.split(":", 1)
+        try:
+            out[k.strip()] = float(v.strip())
+        except ValueError:
+            out[k.strip()] = v.strip()
+    if out.get("kernel_source_sha256_16") != kernel_hash():
+        return {}
+    return out
+
+
+def stored_traffic(kernel: str, workload: str = "c4"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, if it was taken on the current kernel sources (else None)."""
-    path = counters_path(kernel)
-    if not os.path.exists(path):
+    return stored_counters(kernel, workload).get("hbm_bytes_per_launch")
+
+
+def read_ceiling(g, dev, n_bytes: int = 4 << 30, reps: int = 10) -> dict:
+    """HBM read ceiling of this GPU: the read kernel over a zero-filled
+    n_bytes buffer, median device time of `reps` runs after two warm-ups."""
+    import torch
+    buf = torch.zeros(n_bytes // 4, dtype=torch.int32, device=dev)
+    sink = torch.zeros(4, dtype=torch.int32, device=dev)
+    for _ in range(2):
+        g.gace_read_ceiling(buf, sink)
+    ms = sorted(g.gace_read_ceiling(buf, sink) for _ in range(reps))
+    del buf
+    torch.cuda.empty_cache()
+    med = ms[len(ms) // 2]
+    return dict(gbps=round(n_bytes / (med * 1e-3) / 1e9, 1), best_gbps=round(n_bytes / (ms[0] * 1e-3) / 1e9, 1),
+                bytes=n_bytes, reps=reps, kernel="gace_read_kernel")
+
+
+def cpu_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(cpu_model=model, host_logical_cpus=os.cpu_count())
+
+
+# the oracle's threads: the host cores allotted to one GPU (at most 16)
+CPU_THREADS = min(os.cpu_count() or 1, 16)
+
+
+def stored_expected(name: str, w):
+    """The oracle's stored results for workload `name` (c4 or c5), in the
+    workload's request order, as the tuples the comparisons use; None when the
+    stored file was written for another workload definition (a scaled run)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import expected_io
+    try:
+        d = expected_io.load(name, w)
+    except ValueError:
         return None
-    txt = open(path).read()
-    h = None
-    t = None
-    for line in txt.splitlines():
-        if line.startswith("kernel_source_sha256_16:"):
-            h = line.split(":", 1)[1].strip()
-        if line.startswith("hbm_bytes_per_launch:"):
-            t = float(line.split(":", 1)[1].strip())
-    if h != kernel_hash() or t is None:
-        return None
-    return t
+    out = []
+    for kind, i in w.order:
+        v = d[(kind, i)]
+        if kind == "join":
+            out.append(tuple(v[f] for f in expected_io.JOIN_FIELDS))
+        else:
+            out.append((tuple(v[0]), v[1], v[2]))
+    return out
 
 
 def build_requests(g, w, tabs, keys):
@@ -81,9 +143,12 @@ def build_requests(g, w, tabs, keys):
     return out
 
 
-def cpu_baseline(w, budget_rows_preds: float, nthreads: int):
-    """Oracle rows*predicates/s on a bounded sample: selectivity requests taken
-    in batch order until the sample holds ~budget rows*predicates."""
+def cpu_baseline(w, budget_rows_preds: float, nthreads: int, join_keys_budget: float = 3e7):
+    """The oracle on bounded samples of the batch: selectivity requests taken
+    in batch order until the sample holds ~budget rows*predicates, counted on
+    `nthreads` threads and (a share of them) on one thread; and join requests
+    in batch order until ~join_keys_budget sampled keys, joined by the
+    oracle's sort (one thread)."""
     import numpy as np
 
     import datagen
@@ -104,6 +169,7 @@ def cpu_baseline(w, budget_rows_preds: float, nthreads: int):
         if total > 0.9 * budget_rows_preds:
             break
     secs, rp_done, rows_done = 0.0, 0, 0
+    secs1, rp1, n1 = 0.0, 0, 0
     for i, kb in picked:
         r = w.sel[i]
         t = w.tables[r.table]
@@ -111,18 +177,54 @@ def cpu_baseline(w, budget_rows_preds: float, nthreads: int):
                                     for b in kb])
         cols = [np.concatenate([datagen.host_column(c, e - b, row0=b, nthreads=nthreads) for b, e in spans])
                 for c in t.cols]
+        dts = [c.dtype for c in t.cols]
         t0 = time.perf_counter()
-        counts, sampled, _ = oracle.probe_selectivity(cols, [c.dtype for c in t.cols], t.table_id, r.preds,
-                                                      0, 1.0, 1 << 20, nthreads)
+        counts, sampled, _ = oracle.probe_selectivity(cols, dts, t.table_id, r.preds, 0, 1.0, 1 << 20, nthreads)
         secs += time.perf_counter() - t0
         rp_done += sampled * len(r.preds)
         rows_done += sampled
+        if rp1 + sampled * len(r.preds) <= budget_rows_preds / nthreads:
+            t0 = time.perf_counter()
+            c1, _, _ = oracle.probe_selectivity(cols, dts, t.table_id, r.preds, 0, 1.0, 1 << 20, 1)
+            secs1 += time.perf_counter() - t0
+            assert c1.tolist() == counts.tolist()
+            rp1 += sampled * len(r.preds)
+            n1 += 1
         del cols
-    return dict(value=rp_done / secs if secs > 0 else None, unit="rows*predicates/s", cores=nthreads,
-                kind="oracle", seconds=round(secs, 3),
-                sample="%d of %d selectivity requests in batch order (%d sampled rows, %.3g rows*predicates); "
-                       "kept-block rows regenerated on the host, counting timed"
-                       % (len(picked), len(w.sel), rows_done, rp_done))
+    # joins: the oracle's sort-based frequency join on the regenerated kept keys
+    jsecs, jkeys, jn = 0.0, 0, 0
+    for kind, j in w.order:
+        if kind != "join":
+            continue
+        jr = w.joins[j]
+        est = 0
+        for side, sp in ((jr.r, jr.spec_r), (jr.s, jr.spec_s)):
+            kb = oracle.kept_blocks(side.n_rows, sp.seed, side.table_id, sp.rate, sp.block_rows)
+            est += len(kb) * sp.block_rows
+        if est == 0 or jkeys + est > join_keys_budget:
+            continue
+        kr = oracle.sampled_keys(jr.r, jr.spec_r, nthreads)
+        ks = oracle.sampled_keys(jr.s, jr.spec_s, nthreads)
+        t0 = time.perf_counter()
+        oracle.join_freq(kr, jr.r.table_id, 0, 1.0, 1 << 20, ks, jr.s.table_id, 0, 1.0, 1 << 20)
+        jsecs += time.perf_counter() - t0
+        jkeys += len(kr) + len(ks)
+        jn += 1
+        del kr, ks
+    out = dict(value=rp_done / secs if secs > 0 else None, unit="rows*predicates/s", cores=nthreads,
+               kind="oracle", seconds=round(secs, 3),
+               sample="%d of %d selectivity requests in batch order (%d sampled rows, %.3g rows*predicates); "
+                      "kept-block rows regenerated on the host, counting timed"
+                      % (len(picked), len(w.sel), rows_done, rp_done),
+               t1=dict(value=rp1 / secs1 if secs1 > 0 else None, unit="rows*predicates/s", cores=1,
+                       seconds=round(secs1, 3),
+                       sample="the first %d of those requests (%.3g rows*predicates), same counts" % (n1, rp1)),
+               join=dict(value=jkeys / jsecs if jsecs > 0 else None, unit="sampled join keys/s", cores=1,
+                         seconds=round(jsecs, 3),
+                         sample="%d of %d join requests in batch order (%d sampled keys, R + S), sort-based "
+                                "frequency join timed" % (jn, len(w.joins), jkeys)))
+    out.update(cpu_info())
+    return out
 
 
 # ---------------------------------------------------------------- serving
@@ -180,7 +282,8 @@ def serve_point(g, pool_arr, expect, kinds, qps, cfg, seed, duration_s=10.0, max
     requests), each request drawn uniformly from the pool.  Latency = the
     server's completion time - the scheduled arrival time; arrivals in the
     first warm_s seconds are not counted.  Every served result is compared
-    with the pool entry's plain-path result."""
+    with the pool entry's expected result (the oracle's stored one at full
+    size)."""
     import ctypes
     import queue as _q
     import threading
@@ -214,7 +317,7 @@ def serve_point(g, pool_arr, expect, kinds, qps, cfg, seed, duration_s=10.0, max
             p = int(picks[i])
             if kinds[p] == "join":
                 o = jres[slot]
-                got = (int(o.join_card), int(o.ndv_R), int(o.ndv_S), int(o.n_R), int(o.n_S))
+                got = tuple(int(getattr(o, f)) for f in JOIN_FIELDS)
             else:
                 k = len(expect[p][0])
                 got = (tuple(int(x) for x in counts[slot][:k]), int(infos[slot].sampled_rows),
@@ -299,7 +402,7 @@ def serve_main(args):
         s0 = time.perf_counter()
         if isinstance(q, g.JoinRequest):
             r = g.gace_join_freq(ctx, q.R, q.S)
-            expect.append((r["join_card"], r["ndv_R"], r["ndv_S"], r["n_R"], r["n_S"]))
+            expect.append(tuple(r[f] for f in JOIN_FIELDS))
         else:
             c, nrow, nblk = g.gace_probe_selectivity(ctx, q.table, q.preds, q.seed, q.rate, q.block_rows)
             expect.append((tuple(int(x) for x in c), nrow, nblk))
@@ -308,6 +411,14 @@ def serve_main(args):
     plain_s = time.time() - t0
     print("[serve] plain path over the pool: %.1fs (%.1f req/s)" % (plain_s, len(pool) / plain_s), file=sys.stderr,
           flush=True)
+    # served results are compared with the oracle's stored pool results (at
+    # full size), which the plain path must equal too
+    oracle_expect = stored_expected("c5", w)
+    plain_vs_oracle = None
+    if oracle_expect is not None:
+        plain_vs_oracle = sum(a != b for a, b in zip(expect, oracle_expect))
+        expect = oracle_expect
+    reference = "oracle (stored pool results)" if oracle_expect is not None else "plain path (scaled run)"
     free_b, _ = torch.cuda.mem_get_info()
     ws = int(min(args.serve_workspace_gb * (1 << 30), free_b * 0.8))
     modes = {
@@ -335,7 +446,8 @@ def serve_main(args):
                                   "" if args.scale == 1.0 else " (scale %g)" % args.scale),
                    "arrivals": "open-loop Poisson, %gs or 20000 requests per point, first 1s not counted"
                                % args.serve_seconds},
-        "plain_path_pool": {"seconds": round(plain_s, 3),
+        "served_results_compared_with": reference,
+        "plain_path_pool": {"seconds": round(plain_s, 3), "mismatches_vs_oracle": plain_vs_oracle,
                             "latency_ms_p50": round(_pct(plain_lat, 0.5), 4),
                             "latency_ms_p99": round(_pct(plain_lat, 0.99), 4)},
         "points": points,
@@ -548,9 +660,240 @@ def est_main(args):
                       "truth": {"sel": sel_true, "pcs": pcs_true}, "points": points}))
 
 
+# ---------------------------------------------------------------- configs 1-3
+def _lat(xs):
+    return dict(p50=round(_pct(xs, 0.50), 3), p99=round(_pct(xs, 0.99), 3), min=round(min(xs), 3))
+
+
+def _sel_cpu(cols_host, dtypes, table_id, preds, seed, rate, B, want, min_s=2.0):
+    """The oracle on the same probe: per-probe seconds on CPU_THREADS threads
+    and on one, each repeated until min_s has passed; its counts must equal
+    `want` (the device's)."""
+    import oracle
+    res = {}
+    for T in (CPU_THREADS, 1):
+        n, t_all = 0, 0.0
+        while t_all < min_s or n < 1:
+            t0 = time.perf_counter()
+            got = oracle.probe_selectivity(cols_host, dtypes, table_id, preds, seed, rate, B, T)
+            t_all += time.perf_counter() - t0
+            n += 1
+        if got[0].tolist() != want[0].tolist() or got[1] != want[1]:
+            raise RuntimeError("device counts differ from the oracle's")
+        res[T] = (t_all / n, n)
+    return res
+
+
+def config_sel_main(args, cfg: int):
+    """Configs 1 and 2: one selectivity probe on the plain path (call to
+    results on the host), repeated; latency percentiles, device time of the
+    scan kernel from its HIP events, and the same probe on the allocation-free
+    entry point."""
+    import torch
+
+    import datagen
+    import paper_2512_19750_amd as g
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ceiling = read_ceiling(g, dev)
+    w = datagen.config1() if cfg == 1 else datagen.config2()
+    t = w.tables[0]
+    req = w.sel[0]
+    sp = req.spec
+    t_setup = time.time()
+    cols = datagen.device_table(t, dev)
+    torch.cuda.synchronize()
+    print("[bench] config %d: %d rows x %d columns generated in %.1fs" % (cfg, t.n_rows, len(t.cols),
+                                                                         time.time() - t_setup),
+          file=sys.stderr, flush=True)
+    tab = g.Table(cols, t.table_id)
+    ctx = g.gace_create(0, 1 << 30)
+    reps = args.reps or (2000 if cfg == 1 else 300)
+    for _ in range(args.warmup * 10):
+        got = g.gace_probe_selectivity(ctx, tab, req.preds, sp.seed, sp.rate, sp.block_rows)
+    lat, kern = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        got = g.gace_probe_selectivity(ctx, tab, req.preds, sp.seed, sp.rate, sp.block_rows)
+        lat.append((time.perf_counter() - t0) * 1e6)
+        ks = g.gace_last_kernel_stats(ctx)
+        kern.append(ks["scan_ms"] * 1e3)
+    alg = ks["scan_alg_bytes"]
+    compile_us = ks["compile_ms"] * 1e3
+    g.gace_destroy(ctx)
+    na = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        got_na = g.gace_probe_selectivity_noalloc(tab, req.preds, sp.seed, sp.rate, sp.block_rows)
+        na.append((time.perf_counter() - t0) * 1e6)
+    if got_na[0].tolist() != got[0].tolist() or got_na[1:] != got[1:]:
+        raise RuntimeError("allocation-free probe differs from the context path")
+    sampled, n_preds = got[1], len(req.preds)
+    k_mean = sum(kern) / len(kern)
+    achieved = alg / (k_mean * 1e-6) / 1e9
+    p50 = _pct(lat, 0.5)
+    cpu = None
+    if not args.no_cpu:
+        host = [c.cpu().numpy() for c in cols]
+        if cfg == 2:        # the kept blocks only (1 % of the rows), regenerated as the oracle does
+            import oracle
+            kb = oracle.kept_blocks(t.n_rows, sp.seed, t.table_id, sp.rate, sp.block_rows)
+            rows = np.concatenate([np.arange(int(b) * sp.block_rows, min(t.n_rows, (int(b) + 1) * sp.block_rows))
+                                   for b in kb]) if len(kb) else np.zeros(0, dtype=np.int64)
+            host = [h[rows] for h in host]
+            seed, rate, B = 0, 1.0, 1 << 20
+            sample = "the probe's %d kept blocks (%d rows), counted on the host" % (len(kb), len(rows))
+        else:
+            seed, rate, B = sp.seed, sp.rate, sp.block_rows
+            sample = "the whole probe (%d rows)" % t.n_rows
+        r = _sel_cpu(host, [c.dtype for c in t.cols], t.table_id, req.preds, seed, rate, B, got)
+        cpu = dict(value=r[CPU_THREADS][0] * 1e6, unit="us per probe", cores=CPU_THREADS, kind="oracle",
+                   sample=sample + ", repeated %d times; counts equal the device's" % r[CPU_THREADS][1],
+                   t1=dict(value=r[1][0] * 1e6, unit="us per probe", cores=1, repeats=r[1][1]),
+                   rows_predicates_per_s=sampled * n_preds / r[CPU_THREADS][0])
+        cpu.update(cpu_info())
+    sq = stored_counters("gace_scan_kernel", "c%d" % cfg)
+    valu = sq.get("sq_insts_valu_per_launch")
+    salu = sq.get("sq_insts_salu_per_launch")
+    out = {
+        "metric": "plain single-probe latency (call to counts on the host), p50",
+        "value": round(p50, 3),
+        "unit": "us",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": args.warmup * 10,
+        "ms_per_step": round(p50 / 1e3, 6),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32" if cfg == 1 else "int32,int64,f32",
+        "data": "synthetic (seeded counter-based generator, generated in HBM)",
+        "config": {"workload": ("C1 plain single probe: 1,000,000 rows x 4 int32 U[0,1000), c0 in [100,300) AND "
+                                "c1 in [0,500), rate 1" if cfg == 1 else
+                                "C2 skewed correlated multi-predicate probe: 100M rows x 8 columns (Zipf 1.1, "
+                                "Zipf 1.1 + noise, Zipf 1.3, uniform i32, 2 uniform i64, 2 uniform f32), 64 "
+                                "predicates of 2-4 terms, block-Bernoulli 1 %, 4096-row blocks"),
+                   "sampled_rows": sampled, "kept_blocks": got[2], "predicates": n_preds},
+        "latency_us": _lat(lat),
+        "scan_kernel_us": _lat(kern),
+        "host_compile_us": round(compile_us, 3),
+        "noalloc_latency_us": _lat(na),
+        "rows_predicates_per_s": sampled * n_preds / (p50 * 1e-6),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": stored_traffic("gace_scan_kernel", "c%d" % cfg), "kernel": "gace_scan_kernel",
+                     "alg_bytes_per_launch": alg, "kernel_us": round(k_mean, 3),
+                     "read_ceiling_gbps": ceiling["gbps"]},
+        "issue_counts": None if valu is None else {
+            "kernel": "gace_scan_kernel", "sq_insts_valu_per_launch": valu, "sq_insts_salu_per_launch": salu,
+            "valu_lane_ops_per_sampled_row": round(valu * 64 / max(sampled, 1), 2),
+            "valu_lane_ops_per_alg_byte": round(valu * 64 / max(alg, 1), 3)},
+        "read_ceiling": ceiling,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def config3_main(args):
+    """Config 3: the join-key frequency probe on the plain path at 100 % and
+    5 % sampling; keys/s of the call, and the join stage's device time from its
+    HIP events against its algorithmic bytes."""
+    import torch
+
+    import datagen
+    import paper_2512_19750_amd as g
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ceiling = read_ceiling(g, dev)
+    w1 = datagen.config3(1.0)
+    jr = w1.joins[0]
+    t_setup = time.time()
+    kr = datagen.device_column(jr.r.cols[0], jr.r.n_rows, dev)
+    ks = datagen.device_column(jr.s.cols[0], jr.s.n_rows, dev)
+    torch.cuda.synchronize()
+    print("[bench] config 3: %d + %d keys generated in %.1fs" % (jr.r.n_rows, jr.s.n_rows, time.time() - t_setup),
+          file=sys.stderr, flush=True)
+    ctx = g.gace_create(0, 24 << 30)
+    lines = []
+    for rate in (1.0, 0.05):
+        w = datagen.config3(rate)
+        j = w.joins[0]
+        R = g.Keys(kr, j.r.table_id, j.spec_r.seed, rate, j.spec_r.block_rows)
+        S = g.Keys(ks, j.s.table_id, j.spec_s.seed, rate, j.spec_s.block_rows)
+        steps = args.steps if rate == 1.0 else args.steps * 5
+        for _ in range(args.warmup):
+            res = g.gace_join_freq(ctx, R, S)
+        torch.cuda.synchronize()
+        wall, dev_ms = [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            res = g.gace_join_freq(ctx, R, S)
+            wall.append((time.perf_counter() - t0) * 1e3)
+            st = g.gace_last_kernel_stats(ctx)
+            dev_ms.append(st["join_ms"])
+        keys = res["n_R"] + res["n_S"]
+        alg = st["join_alg_bytes"]
+        jm = sum(dev_ms) / len(dev_ms)
+        wm = _pct(wall, 0.5)
+        achieved = alg / (jm * 1e-3) / 1e9
+        tag = "c3r%d" % round(rate * 100)
+        traffic = stored_traffic("gace_join_stage", tag)
+        cpu = None
+        if not args.no_cpu and rate == 0.05:
+            import oracle
+            r_keys = oracle.sampled_keys(j.r, j.spec_r, CPU_THREADS)
+            s_keys = oracle.sampled_keys(j.s, j.spec_s, CPU_THREADS)
+            t0 = time.perf_counter()
+            want = oracle.join_freq(r_keys, j.r.table_id, 0, 1.0, 1 << 20, s_keys, j.s.table_id, 0, 1.0, 1 << 20)
+            secs = time.perf_counter() - t0
+            if want != res:
+                raise RuntimeError("device join result differs from the oracle's")
+            cpu = dict(value=(len(r_keys) + len(s_keys)) / secs, unit="sampled keys/s", cores=1, kind="oracle",
+                       seconds=round(secs, 3),
+                       sample="the 5 %% probe's %d kept keys (R + S), sort-based frequency join; result equals "
+                              "the device's" % (len(r_keys) + len(s_keys)))
+            cpu.update(cpu_info())
+        lines.append({
+            "metric": "join-key frequency probe: sampled keys/s (call to results on the host)",
+            "value": keys / (wm * 1e-3),
+            "unit": "keys/s",
+            "n_gpus": 1,
+            "steps": steps,
+            "warmup": args.warmup,
+            "ms_per_step": round(wm, 4),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "int64",
+            "data": "synthetic (seeded counter-based generator, generated in HBM)",
+            "config": {"workload": "C3 join-key frequency probe: R 200M int64 Zipf 1.0 over 1e7 keys, S 50M "
+                                   "uniform over the same domain, rate %g, 4096-row blocks" % rate,
+                       "sampled_keys": keys, "ndv_R": res["ndv_R"], "ndv_S": res["ndv_S"],
+                       "join_card": res["join_card"]},
+            "wall_ms": _lat(wall),
+            "join_stage_ms": round(jm, 4),
+            "device_keys_per_s": keys / (jm * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                         "traffic_gbps": None if traffic is None else round(traffic / (jm * 1e-3) / 1e9, 1),
+                         "kernel": "gace_join_stage", "alg_bytes_per_launch": alg, "kernel_ms": round(jm, 4),
+                         "read_ceiling_gbps": ceiling["gbps"]},
+            "read_ceiling": ceiling,
+            "cpu_baseline": cpu,
+        })
+        print("[bench] config 3 rate %g: %.3f ms wall, %.3f ms join stage, %.3g keys/s"
+              % (rate, wm, jm, keys / (wm * 1e-3)), file=sys.stderr, flush=True)
+    g.gace_destroy(ctx)
+    for line in lines:
+        print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4],
+                    help="1/2: plain single-probe latency; 3: join probe at 100 %% and 5 %%; 4: the batch")
+    ap.add_argument("--reps", type=int, default=0, help="probes timed in --config 1/2 (0: 2000 / 300)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0, help="shrink every size (tests only)")
@@ -588,6 +931,12 @@ def main():
               "(multi-GPU sharding is a design note, not a code path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.config in (1, 2):
+        config_sel_main(args, args.config)
+        return
+    if args.config == 3:
+        config3_main(args)
+        return
     if args.serve:
         serve_main(args)
         return
@@ -616,6 +965,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes": args.calib_copy}))
         return
+    ceiling = read_ceiling(g, dev)
+    print("[bench] HBM read ceiling %.0f GB/s (best %.0f)" % (ceiling["gbps"], ceiling["best_gbps"]),
+          file=sys.stderr, flush=True)
     t_setup = time.time()
     w = datagen.config4(scale=args.scale)
     tabs, keys = datagen.materialise(w, dev)
@@ -630,18 +982,16 @@ def main():
     ctx = g.gace_create(0, ws)
     reqs = build_requests(g, w, tabs, keys)
     prepared = g.make_requests(reqs)
-    # the timed region launches directly (below), so the schedule is tuned
-    # in that launch mode
-    g.gace_set_graph(ctx, False)
+    # the timed region replays the captured graph (the batched path's launch),
+    # so the schedule is tuned in that launch mode; the graph holds HIP timing
+    # events around the scan kernel (call's stream) and the join stage (side
+    # stream), read after every step
+    g.gace_set_graph(ctx, True)
     if args.autotune:
         t0 = time.time()
         g.gace_autotune(ctx, reqs, args.tune_cache)
         print("[bench] schedule %s (%.1fs)" % (g.gace_get_schedule(ctx), time.time() - t0), file=sys.stderr,
               flush=True)
-    # timed region: direct launches, so that HIP events bracket each kernel on
-    # its own stream (scan kernel on the call's stream, join kernel on the side
-    # stream); results are identical to graph replay, which is timed after
-    g.gace_set_graph(ctx, False)
     for _ in range(args.warmup):
         g.gace_batch_run(ctx, reqs, prepared=prepared)
     torch.cuda.synchronize()
@@ -661,6 +1011,8 @@ def main():
     rows_preds = st["rows_preds"]
     value = rows_preds / (wall / args.steps)
     kernel_ms = sum(kms) / len(kms)
+    if not ks["timed"] or min(sms) <= 0 or min(jms) <= 0:
+        raise RuntimeError("the graph replay returned no per-kernel times")
     # the join stage is the partitioning kernel followed by the aggregation
     # kernel on one stream; its events bracket both
     per_kernel = {
@@ -674,15 +1026,16 @@ def main():
     dk = per_kernel[dominant]
     achieved = dk["achieved_gbps"]
     traffic = stored_traffic(dominant)
-    # graph replay of the same batch (the batched path's default)
-    g.gace_set_graph(ctx, True)
+    # direct launches of the same batch (the plain path's launch mode), for comparison
+    g.gace_set_graph(ctx, False)
     g.gace_batch_run(ctx, reqs, prepared=prepared)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g.gace_batch_run(ctx, reqs, prepared=prepared)
     torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    direct_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    g.gace_set_graph(ctx, True)
     sel_rows = 0
     join_keys = 0
     for q in reqs:
@@ -692,10 +1045,10 @@ def main():
         else:
             sel_rows += q.result()[1]
     compile_ms = sum(cms) / len(cms)
-    print("[bench] batch %.2f ms/step (host compile %.2f ms, kernels %.2f ms: scan %.2f, join %.2f; graph replay "
-          "%.2f ms/step), %.3g rows*preds/s" % (ms_step, compile_ms, kernel_ms, per_kernel["gace_scan_kernel"]["ms"],
-                                               per_kernel["gace_join_stage"]["ms"], graph_ms, value),
-          file=sys.stderr, flush=True)
+    print("[bench] batch %.2f ms/step graph replay (host compile %.2f ms, kernels %.2f ms: scan %.2f, join %.2f; "
+          "direct launch %.2f ms/step), %.3g rows*preds/s"
+          % (ms_step, compile_ms, kernel_ms, per_kernel["gace_scan_kernel"]["ms"],
+             per_kernel["gace_join_stage"]["ms"], direct_ms, value), file=sys.stderr, flush=True)
 
     plain = None
     gate = None
@@ -708,7 +1061,7 @@ def main():
             s = time.perf_counter()
             if isinstance(q, g.JoinRequest):
                 r = g.gace_join_freq(ctx, q.R, q.S)
-                expect.append((r["join_card"], r["ndv_R"], r["ndv_S"], r["n_R"], r["n_S"]))
+                expect.append(tuple(r[f] for f in JOIN_FIELDS))
             else:
                 c, nrow, nblk = g.gace_probe_selectivity(ctx, q.table, q.preds, q.seed, q.rate, q.block_rows)
                 expect.append((tuple(int(x) for x in c), nrow, nblk))
@@ -726,22 +1079,27 @@ def main():
         print("[bench] gate %s" % json.dumps(gate), file=sys.stderr, flush=True)
     sched = g.gace_get_schedule(ctx)
     g.gace_destroy(ctx)
-    # served: the same requests arriving as an open-loop Poisson stream
+    # served: the same requests arriving as an open-loop Poisson stream; each
+    # result is compared with the oracle's stored result (full size)
     served = None
     if args.plain and args.serve_point_qps > 0:
         kinds = ["join" if isinstance(q, g.JoinRequest) else "sel" for q in reqs]
-        served = serve_point(g, prepared[0], expect, kinds, args.serve_point_qps,
+        oracle_expect = stored_expected("c4", w)
+        ref = expect if oracle_expect is None else oracle_expect
+        served = serve_point(g, prepared[0], ref, kinds, args.serve_point_qps,
                              dict(max_inflight=3, max_batch=64, queue_capacity=4096, workspace_bytes=ws),
                              seed=S_SERVE, duration_s=args.serve_point_seconds)
+        served["compared_with"] = "plain path (scaled run)" if oracle_expect is None else "oracle (stored results)"
+        if oracle_expect is not None:
+            served["plain_mismatches_vs_oracle"] = sum(a != b for a, b in zip(expect, oracle_expect))
         print("[bench] served %s" % json.dumps(served), file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:
-        nthreads = min(os.cpu_count() or 1, 16)
-        cpu = cpu_baseline(w, args.cpu_budget * args.scale, nthreads)
-        print("[bench] oracle %.3g rows*preds/s on %d threads (%.1fs)" % (cpu["value"] or 0, nthreads,
-                                                                         cpu["seconds"]), file=sys.stderr,
-              flush=True)
+        cpu = cpu_baseline(w, args.cpu_budget * args.scale, CPU_THREADS)
+        print("[bench] oracle %.3g rows*preds/s on %d threads (%.1fs), %.3g on 1 (%.1fs); join %.3g keys/s"
+              % (cpu["value"] or 0, CPU_THREADS, cpu["seconds"], cpu["t1"]["value"] or 0, cpu["t1"]["seconds"],
+                 cpu["join"]["value"] or 0), file=sys.stderr, flush=True)
 
     out = {
         "metric": "sampled rows*predicates/s (batched probe), with HBM GB/s, batched-vs-plain and p99 probe latency",
@@ -760,14 +1118,15 @@ def main():
             "workload": "C4 batched uneven probes: 448 selectivity requests (1-32 conjunctive predicates, "
                         "rate log-uniform 0.1-100%%, 4096-row blocks) over 16 tables of log-uniform 1e6-5e8 rows "
                         "x 4 int32 columns + 64 join-key frequency probes (Zipf 1.0 R / uniform S, 0.01-1 x "
-                        "(200M + 50M) keys, rate 1 or 0.05), one batched launch of the persistent scan and join "
-                        "kernels running concurrently%s"
+                        "(200M + 50M) keys, rate 1 or 0.05), one graph-replayed launch of the persistent scan "
+                        "and join kernels running concurrently%s"
                         % ("" if args.scale == 1.0 else " (scale %g)" % args.scale),
             "requests": len(reqs),
             "resident_bytes": resident,
             "sampled_rows": sel_rows,
             "join_keys_sampled": join_keys,
             "rows_predicates_per_step": rows_preds,
+            "launch": "hipGraph replay",
         },
         "schedule": sched,
         "roofline": {
@@ -780,14 +1139,17 @@ def main():
             "kernel": dominant,
             "alg_bytes_per_launch": dk["alg_bytes"],
             "kernel_ms": round(dk["ms"], 4),
+            "read_ceiling_gbps": ceiling["gbps"],
+            "frac_of_read_ceiling": round(achieved / ceiling["gbps"], 4),
         },
         "kernels": {k: dict({"ms": round(v["ms"], 4), "alg_bytes": v["alg_bytes"],
                              "achieved_gbps": round(v["achieved_gbps"], 1),
                              "traffic": stored_traffic(k)}, **({"kernels": v["kernels"]} if "kernels" in v else {}))
                     for k, v in per_kernel.items()},
+        "read_ceiling": ceiling,
         "batch_kernel_span_ms": round(kernel_ms, 4),
         "host_compile_ms": round(compile_ms, 4),
-        "graph_replay_ms_per_step": round(graph_ms, 4),
+        "direct_launch_ms_per_step": round(direct_ms, 4),
         "join_keys_per_s": join_keys / (wall / args.steps),
         "served": served,
         "plain_path": plain,

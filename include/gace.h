@@ -255,14 +255,15 @@ gace_status gace_set_schedule(gace_ctx* ctx, const gace_schedule* s);
 gace_status gace_last_batch_stats(gace_ctx* ctx, double* kernel_ms, uint64_t* alg_bytes,
                                   uint64_t* rows_preds);
 
-/* Per-kernel timing of the last gace_batch_run that ran by direct launch
-   (gace_set_graph(ctx, 0)): device time of the scan kernel, measured with HIP
+/* Per-kernel timing of the last gace_batch_run: device time of the scan kernel, measured with HIP
    events on the call's stream, and of the join stage (the partitioning
    kernel followed by the aggregation kernel), measured on the context's side
    stream where it runs concurrently; with the algorithmic HBM bytes of each
    (scan: kept rows x referenced column widths per shared scan; join: 8 bytes
    per sampled key + 16 bytes per distinct key and side).
-   timed = 0 and both times 0 after a graph-replayed batch.  compile_ms is
+   Both launch modes time the kernels: a captured graph holds the same
+   timing events as event record nodes around its kernel nodes (timed = 1
+   once a batch ran).  compile_ms is
    the host time spent validating and compiling the batch's requests into
    the device plan (either launch mode). */
 typedef struct {
@@ -309,6 +310,17 @@ typedef struct {
 gace_status gace_set_trace(gace_ctx* ctx, int enable);
 /* Copies up to cap records of the last batch; *n receives the total. */
 gace_status gace_get_trace(gace_ctx* ctx, gace_trace_rec* out, uint32_t cap, uint32_t* n, double* ticks_per_us);
+
+/* ---------------------------------------------------------------- measurement */
+/* The GPU's HBM read ceiling, reported beside the probe kernels' bandwidth:
+   reads n_bytes (a nonzero multiple of 16) of device memory at `data`
+   (16-byte aligned) with 16-byte nontemporal loads, 64 KiB per workgroup,
+   and returns the kernel's device time in *ms, measured with HIP events on
+   `stream` (the call waits for it).  `sink`: one device word that the kernel
+   writes only if a thread's XOR of its words is all ones (never, for
+   zero-filled memory).  Errors: GACE_EINVAL (NULL pointer, misaligned or
+   empty range), GACE_EDEVICE. */
+gace_status gace_read_ceiling(const void* data, uint64_t n_bytes, uint32_t* sink, double* ms, void* stream);
 
 /* ---------------------------------------------------------------- serving */
 typedef struct {

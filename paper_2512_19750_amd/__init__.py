@@ -186,6 +186,7 @@ ABI_FUNCTIONS = [
     "gace_zonemap_build", "gace_zonemap_destroy", "gace_zonemap_info", "gace_zonemap_read",
     "gace_probe_selectivity_zm",
     "gace_probe_selectivity_noalloc",
+    "gace_read_ceiling",
 ]
 
 _lib = None
@@ -213,6 +214,7 @@ def lib():
             "gace_probe_selectivity": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
                                         ctypes.POINTER(gace_sample_spec), ctypes.POINTER(ctypes.c_uint64),
                                         ctypes.POINTER(gace_probe_info), P], i32),
+            "gace_read_ceiling": ([P, u64, P, ctypes.POINTER(ctypes.c_double), P], i32),
             "gace_probe_selectivity_noalloc": ([ctypes.POINTER(gace_table), ctypes.POINTER(gace_predicates),
                                                 ctypes.POINTER(gace_sample_spec), ctypes.POINTER(ctypes.c_uint64),
                                                 ctypes.POINTER(gace_probe_info), P], i32),
@@ -502,6 +504,16 @@ def gace_probe_selectivity_noalloc(table: Table, preds, seed: int = 0, rate: flo
                                                 counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                                 ctypes.byref(info), _stream_handle(stream)))
     return counts[:len(preds)], int(info.sampled_rows), int(info.kept_blocks)
+
+
+def gace_read_ceiling(data, sink, stream=None) -> float:
+    """Device ms of one read of the whole device tensor `data` (16-byte
+    aligned, a multiple of 16 bytes) by the read-ceiling kernel; sink: a
+    device tensor of at least 4 bytes."""
+    ms = ctypes.c_double()
+    _check(lib().gace_read_ceiling(ctypes.c_void_p(data.data_ptr()), data.numel() * data.element_size(),
+                                   ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ms), _stream_handle(stream)))
+    return ms.value
 
 
 def gace_join_freq(ctx: int, R: Keys, S: Keys, stream=None) -> dict:

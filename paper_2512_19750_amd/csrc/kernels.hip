@@ -1925,6 +1925,30 @@ __device__ void zone_minmax(const T* col, uint64_t n_rows, T* zmin, T* zmax, uin
     }
 }
 
+// HBM read ceiling: workgroup w reads the 16-byte words [w, w + 1) x kWG x
+// kReadUnroll of the buffer (clipped at n16), each thread kReadUnroll words
+// kWG apart with nontemporal loads, all in flight at once, folded with XOR.
+// A thread stores only when its fold is all ones, which never happens on the
+// zero-filled buffers it is measured on: the kernel reads and does not write.
+constexpr uint32_t kReadUnroll = 16;
+__global__ void __launch_bounds__(kWG) gace_read_kernel(const u32x4* p, uint64_t n16, uint32_t* sink) {
+    const uint64_t base = (uint64_t)blockIdx.x * kWG * kReadUnroll + threadIdx.x;
+    const GACE_GLOBAL u32x4* q = (const GACE_GLOBAL u32x4*)p;
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    if (base + (uint64_t)(kReadUnroll - 1) * kWG < n16) {
+        u32x4 v[kReadUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kReadUnroll; ++u) v[u] = __builtin_nontemporal_load(q + base + u * kWG);
+#pragma unroll
+        for (uint32_t u = 0; u < kReadUnroll; ++u) acc ^= v[u];
+    } else {
+        for (uint32_t u = 0; u < kReadUnroll; ++u)
+            if (base + u * kWG < n16) acc ^= __builtin_nontemporal_load(q + base + u * kWG);
+    }
+    const uint32_t f = acc[0] ^ acc[1] ^ acc[2] ^ acc[3];
+    if (f == 0xffffffffu) sink[0] = f;
+}
+
 __global__ void __launch_bounds__(kWG) gace_zone_build_kernel(const void* col, uint32_t dtype, uint64_t n_rows,
                                                               void* zmin, void* zmax) {
     __shared__ __align__(16) uint8_t lds[2 * kWaves * 8];
@@ -2013,6 +2037,7 @@ hipError_t gace_launch_zone_build(const void* col, uint32_t dtype, uint64_t n_ro
                                   hipStream_t stream) {
     const uint64_t zones = (n_rows + gace::kZoneRows - 1) / gace::kZoneRows;
     if (zones == 0) return hipSuccess;
+    (void)hipGetLastError();   // report this launch's error, not an earlier call's
     hipLaunchKernelGGL(gace::gace_zone_build_kernel, dim3((uint32_t)zones), dim3(gace::kWG), 0, stream, col, dtype,
                        n_rows, zmin, zmax);
     return hipGetLastError();
@@ -2022,6 +2047,7 @@ hipError_t gace_launch_zone_prune(const void* zc, const void* terms, const uint3
                                   uint64_t n_zones, uint32_t* skip, void* n_skip, hipStream_t stream) {
     const uint64_t grid = (n_zones + gace::kWG - 1) / gace::kWG;
     if (grid == 0) return hipSuccess;
+    (void)hipGetLastError();   // report this launch's error, not an earlier call's
     hipLaunchKernelGGL(gace::gace_zone_prune_kernel, dim3((uint32_t)grid), dim3(gace::kWG), 0, stream,
                        (const gace::ZoneCol*)zc, (const gace::ZTerm*)terms, pred_off, n_preds, n_zones, skip,
                        (unsigned long long*)n_skip);
@@ -2033,14 +2059,39 @@ hipError_t gace_launch_sample_mask(uint64_t n_blocks, uint64_t seed, uint32_t ta
     const uint64_t words = (n_blocks + 31) / 32;
     const uint64_t grid = (words + gace::kWG - 1) / gace::kWG;
     if (grid == 0) return hipSuccess;
+    (void)hipGetLastError();   // report this launch's error, not an earlier call's
     hipLaunchKernelGGL(gace::gace_sample_mask_kernel, dim3((uint32_t)grid), dim3(gace::kWG), 0, stream, n_blocks,
                        seed, table_id, thr, (uint32_t*)mask);
     return hipGetLastError();
 }
 
+hipError_t gace_launch_read(const void* p, uint64_t n16, void* sink, hipStream_t stream) {
+    const uint64_t per = (uint64_t)gace::kWG * gace::kReadUnroll;
+    const uint64_t grid = (n16 + per - 1) / per;
+    if (grid == 0) return hipSuccess;
+    (void)hipGetLastError();   // report this launch's error, not an earlier call's
+    hipLaunchKernelGGL(gace::gace_read_kernel, dim3((uint32_t)grid), dim3(gace::kWG), 0, stream,
+                       (const gace::u32x4*)p, n16, (uint32_t*)sink);
+    return hipGetLastError();
+}
+
+// host-side handles of the batch kernels, as the kernel nodes of a captured
+// graph name them: 0 scan, 1 join (large tiles), 2 join (small tiles), 3
+// aggregation
+const void* gace_kernel_handle(int which) {
+    switch (which) {
+        case 0: return reinterpret_cast<const void*>(&gace::gace_scan_kernel);
+        case 1: return reinterpret_cast<const void*>(&gace::gace_join_kernel<gace::kPerBig>);
+        case 2: return reinterpret_cast<const void*>(&gace::gace_join_kernel<gace::kPerSmall>);
+        case 3: return reinterpret_cast<const void*>(&gace::gace_agg_kernel);
+        default: return nullptr;
+    }
+}
+
 // launchers used by the host runtime (internal; not part of the public ABI)
 hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,
                             hipStream_t stream) {
+    (void)hipGetLastError();   // report this launch's error, not an earlier call's
     hipLaunchKernelGGL(gace::gace_init_kernel, dim3(256), dim3(gace::kWG), 0, stream, (const uint8_t*)plan,
                        (uint32_t*)head, (unsigned long long*)counts, (unsigned long long*)hist,
                        (gace::JoinAcc*)accs, (gace::Arena*)arena);
@@ -2049,6 +2100,7 @@ hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hi
 
 hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream) {
     const gace::BatchArgs& a = *(const gace::BatchArgs*)args;
+    (void)hipGetLastError();   // report this launch's error, not an earlier call's
     hipLaunchKernelGGL(gace::gace_scan_kernel, dim3(grid), dim3(gace::kWG), gace::kLdsBytes, stream, a);
     return hipGetLastError();
 }
@@ -2056,12 +2108,14 @@ hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream)
 hipError_t gace_launch_agg(const void* args, uint32_t grid, hipStream_t stream) {
     const gace::BatchArgs& a = *(const gace::BatchArgs*)args;
     const uint32_t lds = gace::kLdsMisc + a.agg_slots * 16 + 512;
+    (void)hipGetLastError();   // report this launch's error, not an earlier call's
     hipLaunchKernelGGL(gace::gace_agg_kernel, dim3(grid), dim3(gace::kWG), lds, stream, a);
     return hipGetLastError();
 }
 
 hipError_t gace_launch_join(const void* args, uint32_t grid, int beside_scan, hipStream_t stream) {
     const gace::BatchArgs& a = *(const gace::BatchArgs*)args;
+    (void)hipGetLastError();   // report this launch's error, not an earlier call's
     if (beside_scan)
         hipLaunchKernelGGL(gace::gace_join_kernel<gace::kPerSmall>, dim3(grid), dim3(gace::kWG),
                            gace::join_lds_bytes(gace::kPerSmall * gace::kWG), stream, a);

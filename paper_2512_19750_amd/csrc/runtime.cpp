@@ -110,19 +110,18 @@ static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, 
     if (joins) {
         HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
         HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
-        if (timed) HIP_TRY(hipEventRecord(c->ev_j0, side), "event");
+        if (timed) HIP_TRY(hipEventRecord(c->ev_j0, side), "join start event");
         // the join kernel's smaller-tile variant leaves room on each CU for
         // the scan kernel's workgroup
         HIP_TRY(gace_launch_join(&a, join_grid(c), beside ? 1 : 0, side), "join kernel");
         HIP_TRY(gace_launch_agg(&a, agg_grid(c), side), "aggregation kernel");
-        if (timed) HIP_TRY(hipEventRecord(c->ev_j1, side), "event");
-    } else if (timed) {
-        HIP_TRY(hipEventRecord(c->ev_j0, st), "event");
-        HIP_TRY(hipEventRecord(c->ev_j1, st), "event");
+        if (timed) HIP_TRY(hipEventRecord(c->ev_j1, side), "join end event");
     }
-    if (timed) HIP_TRY(hipEventRecord(c->ev_s0, st), "event");
-    if (scans) HIP_TRY(gace_launch_scan(&a, scan_grid(c, beside), st), "scan kernel");
-    if (timed) HIP_TRY(hipEventRecord(c->ev_s1, st), "event");
+    if (scans) {
+        if (timed) HIP_TRY(hipEventRecord(c->ev_s0, st), "scan start event");
+        HIP_TRY(gace_launch_scan(&a, scan_grid(c, beside), st), "scan kernel");
+        if (timed) HIP_TRY(hipEventRecord(c->ev_s1, st), "scan end event");
+    }
     if (joins) {
         HIP_TRY(hipEventRecord(c->ev_join, side), "join event");
         HIP_TRY(hipStreamWaitEvent(st, c->ev_join, 0), "join wait");
@@ -141,6 +140,57 @@ static void drop_graph(gace_ctx* c) {
     for (int k = 0; k < 8; ++k) drop_graph(c, k);
 }
 
+// Brackets the kernel nodes first .. last of a captured graph with event
+// record nodes for e0 (before first, after first's dependencies) and e1
+// (after last), so a replay times them as the direct launch's events do.
+static gace_status bracket_nodes(hipGraph_t g, hipGraphNode_t first, hipGraphNode_t last, hipEvent_t e0,
+                                 hipEvent_t e1) {
+    size_t nd = 0;
+    HIP_TRY(hipGraphNodeGetDependencies(first, nullptr, &nd), "graph node dependencies");
+    std::vector<hipGraphNode_t> deps(nd);
+    if (nd) HIP_TRY(hipGraphNodeGetDependencies(first, deps.data(), &nd), "graph node dependencies");
+    hipGraphNode_t r0 = nullptr, r1 = nullptr;
+    HIP_TRY(hipGraphAddEventRecordNode(&r0, g, deps.data(), nd, e0), "graph event node");
+    HIP_TRY(hipGraphAddDependencies(g, &r0, &first, 1), "graph dependency");
+    HIP_TRY(hipGraphAddEventRecordNode(&r1, g, &last, 1, e1), "graph event node");
+    return GACE_OK;
+}
+
+// Adds the per-kernel timing events to a captured batch graph: the scan
+// kernel between ev_s0 and ev_s1, the join stage (partitioning kernel, then
+// aggregation kernel) between ev_j0 and ev_j1.  Kernel nodes are found by
+// the kernels' host-side handles.
+static gace_status add_timing_nodes(gace_ctx* c, hipGraph_t g, bool& timed) {
+    size_t n = 0;
+    HIP_TRY(hipGraphGetNodes(g, nullptr, &n), "graph nodes");
+    std::vector<hipGraphNode_t> nodes(n);
+    if (n) HIP_TRY(hipGraphGetNodes(g, nodes.data(), &n), "graph nodes");
+    const void* h_scan = gace_kernel_handle(0);
+    const void* h_join[2] = {gace_kernel_handle(1), gace_kernel_handle(2)};
+    const void* h_agg = gace_kernel_handle(3);
+    hipGraphNode_t scan = nullptr, join = nullptr, agg = nullptr;
+    int n_kernels = 0;
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType t;
+        HIP_TRY(hipGraphNodeGetType(nd, &t), "graph node type");
+        if (t != hipGraphNodeTypeKernel) continue;
+        ++n_kernels;
+        hipKernelNodeParams p;
+        HIP_TRY(hipGraphKernelNodeGetParams(nd, &p), "graph kernel node");
+        if (p.func == h_scan) scan = nd;
+        else if (p.func == h_join[0] || p.func == h_join[1]) join = nd;
+        else if (p.func == h_agg) agg = nd;
+    }
+    // init kernel + scan and / or join + aggregation: every kernel identified
+    timed = n_kernels == 1 + (scan ? 1 : 0) + (join ? 1 : 0) + (agg ? 1 : 0) && (join != nullptr) == (agg != nullptr);
+    if (!timed) return GACE_OK;
+    if (scan)
+        if (gace_status s = bracket_nodes(g, scan, scan, c->ev_s0, c->ev_s1)) return s;
+    if (join)
+        if (gace_status s = bracket_nodes(g, join, agg, c->ev_j0, c->ev_j1)) return s;
+    return GACE_OK;
+}
+
 // the graph of batch kind k ((scan beside the joins << 2) | (has scans << 1) | has joins) for the
 // current schedule
 static gace_status ensure_graph(gace_ctx* c, int k) {
@@ -156,6 +206,12 @@ static gace_status ensure_graph(gace_ctx* c, int k) {
     }
     if (e != hipSuccess) return hip_fail(e, "end capture");
     c->graph[k] = g;
+    bool timed = false;
+    if (gace_status s = add_timing_nodes(c, g, timed)) {
+        drop_graph(c, k);
+        return s;
+    }
+    c->graph_timed[k] = timed;
     HIP_TRY(hipGraphInstantiate(&c->graph_exec[k], g, nullptr, nullptr, 0), "graph instantiate");
     c->graph_sched[k] = c->sched;
     return GACE_OK;
@@ -183,18 +239,19 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, plan_b, hipMemcpyHostToDevice, st), "plan upload");
     if (items_b)
         HIP_TRY(hipMemcpyAsync(c->d_items, c->h_stage + kPlanCap, items_b, hipMemcpyHostToDevice, st), "item upload");
-    HIP_TRY(hipEventRecord(c->ev0, st), "event");
+    HIP_TRY(hipEventRecord(c->ev0, st), "batch start event");
     const bool beside = scan_beside_joins(cb);
     if (use_graph) {
         const int k = (beside ? 4 : 0) | (cb.sel.empty() ? 0 : 2) | (cb.joins.empty() ? 0 : 1);
         if (gace_status s = ensure_graph(c, k)) return s;
         HIP_TRY(hipGraphLaunch(c->graph_exec[k], st), "graph launch");
+        c->last_timed = c->graph_timed[k];
     } else {
         if (gace_status s = launch_direct(c, st, c->side_stream, true, !cb.sel.empty(), !cb.joins.empty(), beside))
             return s;
+        c->last_timed = true;
     }
-    c->last_timed = !use_graph;
-    HIP_TRY(hipEventRecord(c->ev1, st), "event");
+    HIP_TRY(hipEventRecord(c->ev1, st), "batch end event");
     uint8_t* hc = c->h_result;
     uint8_t* hh = hc + kCountsCap;
     uint8_t* ha = hh + kHistCap;
@@ -209,7 +266,7 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
             HIP_TRY(hipMemcpyAsync(c->last_trace.data(), c->d_trace, cb.items.size() * sizeof(TraceRec),
                                    hipMemcpyDeviceToHost, st), "trace download");
     }
-    HIP_TRY(hipEventRecord(c->ev_done, st), "event");
+    HIP_TRY(hipEventRecord(c->ev_done, st), "batch done event");
     return GACE_OK;
 }
 
@@ -219,8 +276,8 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_kernel_ms = ms;
     c->last_scan_ms = c->last_join_ms = 0.0;
     if (c->last_timed) {
-        if (hipEventElapsedTime(&ms, c->ev_s0, c->ev_s1) == hipSuccess) c->last_scan_ms = ms;
-        if (hipEventElapsedTime(&ms, c->ev_j0, c->ev_j1) == hipSuccess) c->last_join_ms = ms;
+        if (!cb.sel.empty() && hipEventElapsedTime(&ms, c->ev_s0, c->ev_s1) == hipSuccess) c->last_scan_ms = ms;
+        if (!cb.joins.empty() && hipEventElapsedTime(&ms, c->ev_j0, c->ev_j1) == hipSuccess) c->last_join_ms = ms;
     }
     const uint8_t* hc = c->h_result;
     const unsigned long long* counts = (const unsigned long long*)hc;
@@ -500,6 +557,28 @@ gace_status gace_join_freq(gace_ctx* ctx, const gace_keys* R, const gace_keys* S
     r.S = *S;
     r.join = out;
     return run_requests(ctx, &r, 1, nullptr, (hipStream_t)stream, false);
+}
+
+gace_status gace_read_ceiling(const void* data, uint64_t n_bytes, uint32_t* sink, double* ms, void* stream) {
+    if (!data || !sink || !ms || n_bytes == 0 || n_bytes % 16 || (uintptr_t)data % 16) {
+        set_error("read ceiling: NULL pointer, or a range that is empty, misaligned or not a multiple of 16 bytes");
+        return GACE_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    hipError_t e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = gace_launch_read(data, n_bytes / 16, sink, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "read ceiling kernel");
+    *ms = t;
+    return GACE_OK;
 }
 
 gace_status gace_batch_run(gace_ctx* ctx, const gace_request* reqs, uint32_t n, gace_status* per_req, void* stream) {

@@ -50,6 +50,8 @@ hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hi
 hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream);
 hipError_t gace_launch_join(const void* args, uint32_t grid, int beside_scan, hipStream_t stream);
 hipError_t gace_launch_agg(const void* args, uint32_t grid, hipStream_t stream);
+hipError_t gace_launch_read(const void* p, uint64_t n16, void* sink, hipStream_t stream);
+const void* gace_kernel_handle(int which);
 }
 
 
@@ -84,6 +86,7 @@ struct gace_ctx {
     hipGraphExec_t graph_exec[8] = {};
     hipGraph_t graph[8] = {};
     gace_schedule graph_sched[8] = {};
+    bool graph_timed[8] = {};                     // the graph holds the per-kernel timing event nodes
     hipStream_t cap_stream = nullptr, cap_side = nullptr;
     // stats of the last batch
     double last_kernel_ms = 0.0;

@@ -23,69 +23,23 @@ c5 file reuses the c4 file's join lines (c4 must exist first).
 from __future__ import annotations
 
 import argparse
-import hashlib
-import json
 import os
 import sys
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
-if ROOT not in sys.path:
-    sys.path.insert(0, ROOT)
+for p in (ROOT, HERE):
+    if p not in sys.path:
+        sys.path.insert(0, p)
 
 import datagen  # noqa: E402
 import oracle   # noqa: E402
-
-FILES = {"c4": os.path.join(HERE, "c4_expected.txt"), "c5": os.path.join(HERE, "c5_pool_expected.txt")}
-JOIN_FIELDS = ["join_card", "ndv_R", "ndv_S", "n_R", "n_S", "f1_R", "f1_S", "f2_R", "f2_S"]
-
-
-def _col(c):
-    return [c.dtype, c.kind, c.seed, c.table, c.col, c.lo, c.span, repr(c.zipf_s), c.zipf_n,
-            c.noise_lo, c.noise_span, c.base_col]
-
-
-def _table(t):
-    return [t.n_rows, t.table_id, [_col(c) for c in t.cols]]
-
-
-def _spec(s):
-    return [s.seed, repr(float(s.rate)), s.block_rows]
-
-
-def fingerprint(w) -> str:
-    """sha256 of a canonical dump of everything that decides the results."""
-    doc = {
-        "tables": [_table(t) for t in w.tables],
-        "sel": [[r.table, [[[c, op, [repr(v) for v in vals]] for (c, op, vals) in p] for p in r.preds],
-                 _spec(r.spec)] for r in w.sel],
-        "joins": [[_table(j.r), _table(j.s), _spec(j.spec_r), _spec(j.spec_s)] for j in w.joins],
-        "order": [list(o) for o in w.order],
-    }
-    return hashlib.sha256(json.dumps(doc, sort_keys=True).encode()).hexdigest()
+from expected_io import FILES, JOIN_FIELDS, _table, fingerprint, load  # noqa: E402,F401
 
 
 def workload(name: str):
     return datagen.config4() if name == "c4" else datagen.config5()
-
-
-def load(name: str, w=None):
-    """-> {("sel", i): (counts list, sampled, kept), ("join", j): dict}; checks the fingerprint
-    when a workload is given."""
-    out = {}
-    with open(FILES[name]) as f:
-        head = f.readline().split()
-        assert head[0] == "fingerprint"
-        if w is not None and head[1] != fingerprint(w):
-            raise ValueError("%s was written for another workload definition" % FILES[name])
-        for line in f:
-            p = line.split()
-            if p[0] == "sel":
-                out[("sel", int(p[1]))] = ([int(x) for x in p[4:]], int(p[2]), int(p[3]))
-            else:
-                out[("join", int(p[1]))] = dict(zip(JOIN_FIELDS, (int(x) for x in p[2:])))
-    return out
 
 
 def main():

@@ -155,7 +155,7 @@ def test_open_loop_stream_equals_plain(env):
         for q in reqs:
             if isinstance(q, g.JoinRequest):
                 r = g.gace_join_freq(ctx, q.R, q.S)
-                expect.append((r["join_card"], r["ndv_R"], r["ndv_S"], r["n_R"], r["n_S"]))
+                expect.append(tuple(r[f] for f in bench.JOIN_FIELDS))
             else:
                 c, n, b = g.gace_probe_selectivity(ctx, q.table, q.preds, q.seed, q.rate, q.block_rows)
                 expect.append((tuple(int(x) for x in c), n, b))
