@@ -371,7 +371,7 @@ def serve_point(g, pool_arr, expect, kinds, qps, cfg, seed, duration_s=10.0, max
     return dict(qps=qps, offered=n, counted=len(lat), rejected_busy=busy, mismatches=bad[0],
                 p50_ms=round(_pct(lat, 0.50), 3) if lat else None, p99_ms=round(_pct(lat, 0.99), 3) if lat else None,
                 throughput_rps=round(len(lat) / span, 1) if span > 0 else None, batches=stats["batches"],
-                workspace_peak=stats["workspace_peak"])
+                completed_early=stats["completed_early"], workspace_peak=stats["workspace_peak"])
 
 
 def serve_main(args):

@@ -327,20 +327,27 @@ typedef struct {
     uint32_t max_inflight;       /* batches on the device at once (>= 1) */
     uint32_t max_batch;          /* requests per batch */
     uint32_t queue_capacity;     /* submitted but not finished requests */
-    uint32_t reserved;
+    uint32_t flags;              /* GACE_SERVER_* bits; 0 by default */
     uint64_t workspace_bytes;    /* device memory for admitted requests (admission budget) */
 } gace_server_cfg;
+
+/* finish a request only when its whole batch does (no per-request publishing) */
+#define GACE_SERVER_BATCH_COMPLETION 1u
 
 typedef struct {
     uint64_t submitted, completed, rejected, batches;
     uint64_t queued, inflight;
     uint64_t workspace_in_use, workspace_peak;
+    uint64_t completed_early;    /* of completed: finished as their own scan or join did, before their batch */
 } gace_server_stats;
 
 /* The server owns a worker thread, its own streams and workspace on
    hip_device.  Requests are admitted while their workspace fits the budget,
    batched with whatever else is waiting, and launched while earlier batches
-   still run (continuous batching). */
+   still run (continuous batching).  A request is done when its own scan or
+   join finishes on the device, not when its whole batch does: the kernels
+   publish each finished scan's and join's results to pinned host memory and
+   the worker writes that request's outputs and wakes its waiter at once. */
 gace_status gace_server_create(int hip_device, const gace_server_cfg* cfg, gace_server** out);
 /* Enqueue a copy of *req (its host arrays are copied; device buffers and
    output pointers must stay valid until done).  GACE_EBUSY if the queue is
@@ -348,11 +355,12 @@ gace_status gace_server_create(int hip_device, const gace_server_cfg* cfg, gace_
    estimate exceeds one slot's share of the budget. */
 gace_status gace_server_submit(gace_server* srv, const gace_request* req, uint64_t* ticket);
 /* Wait until request `ticket` is done (timeout_ns < 0: forever).  Its status
-   goes to *req_status; GACE_ETIMEOUT if still running. */
+   goes to *req_status; GACE_ETIMEOUT if still running; GACE_EINVAL for an
+   unknown ticket or one another wait has already collected. */
 gace_status gace_server_wait(gace_server* srv, uint64_t ticket, int64_t timeout_ns, gace_status* req_status);
 /* As gace_server_wait, and also returns when the request was submitted and
-   when the server saw its batch finish, in nanoseconds of CLOCK_MONOTONIC
-   (either pointer may be NULL).  Latency = done - arrival. */
+   when the server saw it finish, in nanoseconds of CLOCK_MONOTONIC (either
+   pointer may be NULL).  Latency = done - arrival. */
 gace_status gace_server_wait_times(gace_server* srv, uint64_t ticket, int64_t timeout_ns, gace_status* req_status,
                                    uint64_t* submit_ns, uint64_t* done_ns);
 gace_status gace_server_stats_get(gace_server* srv, gace_server_stats* out);

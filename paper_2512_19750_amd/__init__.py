@@ -104,13 +104,14 @@ class gace_kernel_stats(ctypes.Structure):
 
 class gace_server_cfg(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
-                ("queue_capacity", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("queue_capacity", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("workspace_bytes", ctypes.c_uint64)]
 
 
 class gace_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "batches", "queued",
-                                                "inflight", "workspace_in_use", "workspace_peak")]
+                                                "inflight", "workspace_in_use", "workspace_peak",
+                                                "completed_early")]
 
 
 # gace_gate.h
@@ -598,9 +599,13 @@ def gace_get_trace(ctx: int):
     return arr, tpu.value
 
 
+GACE_SERVER_BATCH_COMPLETION = 1
+
+
 def gace_server_create(device: int = 0, max_inflight: int = 2, max_batch: int = 256,
-                       queue_capacity: int = 4096, workspace_bytes: int = 8 << 30) -> int:
+                       queue_capacity: int = 4096, workspace_bytes: int = 8 << 30, flags: int = 0) -> int:
     cfg = gace_server_cfg()
+    cfg.flags = flags
     cfg.max_inflight = max_inflight
     cfg.max_batch = max_batch
     cfg.queue_capacity = queue_capacity

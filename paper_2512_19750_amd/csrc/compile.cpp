@@ -769,6 +769,10 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         out.joins.push_back(jo);
     }
 
+    // one histogram entry counts the scan kernel's finished workgroups (per-request completion)
+    const uint32_t wg_done_off = n_hist;
+    n_hist += 1;
+
     // ---- items
     // A kept block streams predicate group g only when its draw is below the
     // threshold of the first request owning a bit of g, so a scan's work per
@@ -861,6 +865,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     H.n_items = (uint32_t)out.items.size();
     H.n_scan_items = n_scan_items;
     H.n_join_end = n_join_end;
+    H.wg_done_off = wg_done_off;
     H.arena_static = arena_static;
     std::vector<uint8_t>& blob = out.plan;
     {

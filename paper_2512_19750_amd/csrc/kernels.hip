@@ -66,7 +66,32 @@ struct BatchArgs {
     uint32_t agg_slots;        // aggregation kernel: LDS table slots (power of two)
     TraceRec* trace;           // one record per item when the plan asks for tracing
     uint64_t spin_limit;       // polls before a join's phase wait gives up (0: at once)
+    uint8_t* host_res;         // device address of the pinned result buffer (per-request completion)
+    uint32_t* host_flags;      // device address of the pinned completion flags
 };
+
+// relaxed device-scope read of a value other workgroups updated with atomics
+__device__ __forceinline__ unsigned long long load_agent(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-request completion: n 64-bit words at src (device) copied into the
+// pinned host buffer at byte offset off, by the whole workgroup or (one) by
+// thread 0 alone.  The caller has made the words final: every producer fenced
+// its atomics before announcing its part done.
+__device__ __forceinline__ void copy_to_host(const BatchArgs& a, const unsigned long long* src, uint64_t n,
+                                             uint64_t off, bool one) {
+    unsigned long long* dst = (unsigned long long*)(a.host_res + off);
+    const uint32_t t0 = one ? 0u : threadIdx.x, step = one ? 1u : kWG;
+    for (uint64_t i = t0; i < n; i += step) dst[i] = load_agent(src + i);
+}
+
+// ... then host flag f is raised to the batch number, after the copies
+__device__ __forceinline__ void raise_flag(const BatchArgs& a, const PlanHdr& H, uint32_t f, bool one) {
+    __threadfence_system();
+    if (!one) __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(&a.host_flags[f], H.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // hardware register XCC_ID (s_getreg: id 20, offset 0, 4 bits): which XCD runs this wave
 __device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u; }
@@ -1688,6 +1713,14 @@ __device__ void jagg_item(const BatchArgs& a, const JoinDesc* jd, const Item& it
             if (s1 == 1) atomicAdd(&acc.f1[1], 1ull);
             if (s0 == 2) atomicAdd(&acc.f2[0], 1ull);
             if (s1 == 2) atomicAdd(&acc.f2[1], 1ull);
+            const PlanHdr& H = *(const PlanHdr*)a.plan;
+            if (H.early) {
+                // every worker fenced its adds before counting itself done
+                __threadfence();
+                copy_to_host(a, (const unsigned long long*)&acc, sizeof(JoinAcc) / 8,
+                             kHostAccsOff + (uint64_t)jd->acc * sizeof(JoinAcc), true);
+                raise_flag(a, H, 1 + jd->acc, true);
+            }
         }
     }
 }
@@ -1731,14 +1764,31 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 8))
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ uint32_t s_item;
     const PlanHdr H = *(const PlanHdr*)a.plan;
+    bool worked = false;
     for (;;) {
         const uint32_t idx = pop_item(&a.head[0], 0, &s_item);
         if (idx >= H.n_scan_items) break;
         const uint64_t t0 = (uint64_t)wall_clock64();
         const Item it = a.items[idx];
         scan_item(a, H, it, lds);
+        worked = true;
         __syncthreads();
         trace_item(a, H, idx, it, t0, t0);
+    }
+    if (H.early && H.n_scan_items) {
+        // the last workgroup to finish publishes every counter and histogram;
+        // a workgroup that ran no item has no atomics to release
+        if (worked) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_item = atomicAdd(&a.hist[H.wg_done_off], 1ull) + 1 == gridDim.x ? 1u : 0u;
+        __syncthreads();
+        if (s_item) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            copy_to_host(a, a.counts, H.n_counts, 0, false);
+            copy_to_host(a, a.hist, H.n_hist, kHostHistOff, false);
+            raise_flag(a, H, 0, false);
+        }
     }
 }
 

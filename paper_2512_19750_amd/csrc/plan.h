@@ -49,7 +49,24 @@ struct PlanHdr {
     uint64_t arena_static;   // bytes of the arena holding the joins' per-item tables
     uint32_t trace;          // nonzero: kernels write one TraceRec per item
     uint32_t n_join_end;     // items [n_scan_items, n_join_end) are join partitioning items, the rest aggregation
+    uint32_t early;          // nonzero: the scans and each join publish their results to the host when done
+    uint32_t seq;            // ... raising their host flags to this batch number
+    uint32_t wg_done_off;    // hist entry counting the scan kernel's finished workgroups
+    uint32_t reserved;
 };
+
+// Per-request completion.  When a plan asks for it, the last workgroup of
+// the scan kernel to finish copies all counters and sample histograms, and
+// the last aggregation worker of a join copies its JoinAcc, into the
+// context's pinned result buffer (the layout of the end-of-batch download:
+// counters at 0, histogram at kHostHistOff, accumulators at kHostAccsOff),
+// then stores the batch number into host flag 0 (every selectivity request)
+// or 1 + j (join j).  One release fence per workgroup orders the counter
+// atomics before its exit count; a fence per item would write back and
+// invalidate the L2 hundreds of times per probe.
+constexpr uint64_t kHostHistOff = 8ull << 20;
+constexpr uint64_t kHostAccsOff = 12ull << 20;
+constexpr uint32_t kMaxFlags = 1u << 16;
 
 // per-item trace record (same layout as gace_trace_rec)
 struct TraceRec {
@@ -164,6 +181,8 @@ struct JoinAcc {
     uint32_t next_s2, reserved;
     unsigned long long f1[2], f2[2];        // distinct keys seen exactly once / twice per side
 };
+
+static_assert(sizeof(JoinAcc) % 8 == 0, "JoinAcc is published to the host as 64-bit words");
 
 struct Arena {                              // bump allocator for partition buffers
     unsigned long long used, size;

@@ -74,6 +74,8 @@ static BatchArgsHost make_args(gace_ctx* c) {
     a.agg_slots = agg_slots(c->sched);
     a.trace = c->d_trace;
     a.spin_limit = c->spin_limit;
+    a.host_res = c->d_host_res;
+    a.host_flags = c->d_host_flags;
     return a;
 }
 
@@ -234,7 +236,17 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     if (cb.arena_static > c->arena_bytes) return too_big("join partition tables", cb.arena_static, c->arena_bytes);
 
     std::memcpy(c->h_stage, cb.plan.data(), plan_b);
-    ((PlanHdr*)c->h_stage)->trace = c->trace ? 1u : 0u;
+    PlanHdr* hs = (PlanHdr*)c->h_stage;
+    hs->trace = c->trace ? 1u : 0u;
+    // per-request completion, for batches where a request can finish before
+    // the batch: a join beside other work (publishing costs a release fence
+    // per scan workgroup, which a batch of scans alone or of one join does not
+    // repay); a fresh batch number, which no flag holds yet
+    c->last_early = c->early && c->d_host_res && c->d_host_flags && 1 + hs->n_joins <= kMaxFlags &&
+                    !cb.joins.empty() && (cb.joins.size() > 1 || !cb.sel.empty());
+    if (++c->seq == 0) ++c->seq;
+    hs->early = c->last_early ? 1u : 0u;
+    hs->seq = c->seq;
     std::memcpy(c->h_stage + kPlanCap, cb.items.data(), items_b);
     HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, plan_b, hipMemcpyHostToDevice, st), "plan upload");
     if (items_b)
@@ -270,8 +282,79 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     return GACE_OK;
 }
 
-// after the batch's done event: write per-request outputs
-gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req) {
+// one selectivity request's outputs from the result buffer; returns its
+// sampled rows
+static uint64_t write_sel(const gace_ctx* c, const CompiledBatch& cb, const SelOut& so, const gace_request* reqs) {
+    const unsigned long long* counts = (const unsigned long long*)c->h_result;
+    const unsigned long long* hist = (const unsigned long long*)(c->h_result + kCountsCap);
+    const gace_request& r = reqs[so.req];
+    const ScanDesc& S = cb.scans[so.scan];
+    uint64_t rows = 0, blocks = 0;
+    for (uint32_t k = so.rank + 1; k <= S.n_req; ++k) {
+        rows += hist[S.hist_off + 2 * k];
+        blocks += hist[S.hist_off + 2 * k + 1];
+    }
+    for (uint32_t p = 0; p < so.n_preds; ++p) r.counts[p] = counts[so.count_off + p];
+    if (r.info) {
+        r.info->sampled_rows = rows;
+        r.info->kept_blocks = blocks;
+    }
+    return rows;
+}
+
+// one join request's outputs from the result buffer (untouched if the join
+// failed); returns its status
+static gace_status write_join(const gace_ctx* c, const JoinOut& jo, const gace_request* reqs, bool write) {
+    const JoinAcc& A = ((const JoinAcc*)(c->h_result + kCountsCap + kHistCap))[jo.join];
+    if (A.status == 2) {
+        set_error("workspace arena too small for the partitioned join keys of this batch");
+        return GACE_ENOMEM;
+    }
+    if (A.status == 4) {
+        set_error("a join phase wait on the device gave up before its dependency finished");
+        return GACE_EDEVICE;
+    }
+    if (A.status != 0) {
+        set_error("join aggregation could not split a partition further");
+        return GACE_EDEVICE;
+    }
+    if (write) {
+        gace_join_result* o = reqs[jo.req].join;
+        o->join_card = A.join;
+        o->ndv_R = A.ndv[0];
+        o->ndv_S = A.ndv[1];
+        o->n_R = A.n[0];
+        o->n_S = A.n[1];
+        o->f1_R = A.f1[0];
+        o->f1_S = A.f1[1];
+        o->f2_R = A.f2[0];
+        o->f2_S = A.f2[1];
+    }
+    return GACE_OK;
+}
+
+void collect_published(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, std::vector<char>& done,
+                       std::vector<std::pair<uint32_t, gace_status>>& out) {
+    if (!c->last_early) return;
+    auto flag = [&](uint32_t f) { return __atomic_load_n(&c->h_flags[f], __ATOMIC_ACQUIRE) == c->seq; };
+    if (!cb.sel.empty() && !done[cb.sel[0].req] && flag(0))
+        for (const SelOut& so : cb.sel) {
+            write_sel(c, cb, so, reqs);
+            done[so.req] = 1;
+            out.emplace_back(so.req, GACE_OK);
+        }
+    for (const JoinOut& jo : cb.joins)
+        if (!done[jo.req] && flag(1 + jo.join)) {
+            const gace_status st = write_join(c, jo, reqs, true);
+            done[jo.req] = 1;
+            out.emplace_back(jo.req, st);
+        }
+}
+
+// after the batch's done event: write per-request outputs (except those
+// already written when their scan or join published them)
+gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
+                            const std::vector<char>* done) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->last_kernel_ms = ms;
     c->last_scan_ms = c->last_join_ms = 0.0;
@@ -279,10 +362,8 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
         if (!cb.sel.empty() && hipEventElapsedTime(&ms, c->ev_s0, c->ev_s1) == hipSuccess) c->last_scan_ms = ms;
         if (!cb.joins.empty() && hipEventElapsedTime(&ms, c->ev_j0, c->ev_j1) == hipSuccess) c->last_join_ms = ms;
     }
-    const uint8_t* hc = c->h_result;
-    const unsigned long long* counts = (const unsigned long long*)hc;
-    const unsigned long long* hist = (const unsigned long long*)(hc + kCountsCap);
-    const JoinAcc* accs = (const JoinAcc*)(hc + kCountsCap + kHistCap);
+    const unsigned long long* hist = (const unsigned long long*)(c->h_result + kCountsCap);
+    const JoinAcc* accs = (const JoinAcc*)(c->h_result + kCountsCap + kHistCap);
     uint64_t alg = 0, rp = 0, jalg = 0;
     for (const ScanDesc& S : cb.scans) {
         uint64_t kept_rows = 0;
@@ -290,45 +371,21 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
         alg += kept_rows * S.row_bytes;
     }
     for (const SelOut& so : cb.sel) {
-        const gace_request& r = reqs[so.req];
         const ScanDesc& S = cb.scans[so.scan];
-        uint64_t rows = 0, blocks = 0;
-        for (uint32_t k = so.rank + 1; k <= S.n_req; ++k) {
-            rows += hist[S.hist_off + 2 * k];
-            blocks += hist[S.hist_off + 2 * k + 1];
-        }
-        for (uint32_t p = 0; p < so.n_preds; ++p) r.counts[p] = counts[so.count_off + p];
-        if (r.info) {
-            r.info->sampled_rows = rows;
-            r.info->kept_blocks = blocks;
+        uint64_t rows = 0;
+        if (done && (*done)[so.req]) {
+            for (uint32_t k = so.rank + 1; k <= S.n_req; ++k) rows += hist[S.hist_off + 2 * k];
+        } else {
+            rows = write_sel(c, cb, so, reqs);
         }
         rp += rows * so.n_preds;
         if (per_req) per_req[so.req] = GACE_OK;
     }
     gace_status worst = GACE_OK;
     for (const JoinOut& jo : cb.joins) {
-        const JoinAcc& A = accs[jo.join];
-        const gace_request& r = reqs[jo.req];
-        gace_status s = GACE_OK;
-        if (A.status == 2) {
-            set_error("workspace arena too small for the partitioned join keys of this batch");
-            s = GACE_ENOMEM;
-        } else if (A.status == 4) {
-            set_error("a join phase wait on the device gave up before its dependency finished");
-            s = GACE_EDEVICE;
-        } else if (A.status != 0) {
-            set_error("join aggregation could not split a partition further");
-            s = GACE_EDEVICE;
-        } else {
-            r.join->join_card = A.join;
-            r.join->ndv_R = A.ndv[0];
-            r.join->ndv_S = A.ndv[1];
-            r.join->n_R = A.n[0];
-            r.join->n_S = A.n[1];
-            r.join->f1_R = A.f1[0];
-            r.join->f1_S = A.f1[1];
-            r.join->f2_R = A.f2[0];
-            r.join->f2_S = A.f2[1];
+        const gace_status s = write_join(c, jo, reqs, !(done && (*done)[jo.req]));
+        if (s == GACE_OK) {
+            const JoinAcc& A = accs[jo.join];
             jalg += 8ull * (A.n[0] + A.n[1]) + 16ull * (A.ndv[0] + A.ndv[1]);
         }
         if (per_req) per_req[jo.req] = s;
@@ -475,6 +532,20 @@ gace_status gace_create(int hip_device, uint64_t workspace_bytes, gace_ctx** out
         set_error("pinned staging / event / stream creation failed");
         return GACE_EDEVICE;
     }
+    // completion flags (zeroed: no batch number is 0) and the device
+    // addresses of the pinned buffers the kernels publish into; without
+    // them the context simply never publishes per request
+    if (hipHostMalloc((void**)&c->h_flags, kMaxFlags * sizeof(uint32_t), hipHostMallocDefault) == hipSuccess) {
+        std::memset(c->h_flags, 0, kMaxFlags * sizeof(uint32_t));
+        void* dr = nullptr;
+        void* df = nullptr;
+        if (hipHostGetDevicePointer(&dr, c->h_result, 0) == hipSuccess &&
+            hipHostGetDevicePointer(&df, c->h_flags, 0) == hipSuccess) {
+            c->d_host_res = (uint8_t*)dr;
+            c->d_host_flags = (uint32_t*)df;
+        }
+    }
+    (void)hipGetLastError();
     int wall_khz = 0;
     if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && wall_khz > 0)
         c->ticks_per_us = wall_khz / 1000.0;
@@ -511,6 +582,7 @@ gace_status gace_destroy(gace_ctx* c) {
     if (c->h_hp) (void)hipHostFree(c->h_hp);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_result) (void)hipHostFree(c->h_result);
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
     if (c->ws) (void)hipFree(c->ws);
     delete c;
     return GACE_OK;

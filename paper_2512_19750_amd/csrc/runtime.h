@@ -37,7 +37,12 @@ struct BatchArgsHost {
     uint32_t agg_slots;
     TraceRec* trace;
     uint64_t spin_limit;
+    uint8_t* host_res;
+    uint32_t* host_flags;
 };
+
+static_assert(kHostHistOff == kCountsCap && kHostAccsOff == kCountsCap + kHistCap,
+              "the kernels publish results in the layout of the pinned result buffer");
 
 gace_schedule default_schedule();
 
@@ -76,6 +81,14 @@ struct gace_ctx {
     // pinned host staging
     uint8_t* h_stage = nullptr;     // plan + items upload
     uint8_t* h_result = nullptr;    // counts + hist + accs download
+    // per-request completion: kernels write finished scans' and joins'
+    // results into h_result and raise their flags (device addresses of both)
+    uint32_t* h_flags = nullptr;
+    uint8_t* d_host_res = nullptr;
+    uint32_t* d_host_flags = nullptr;
+    bool early = false;             // ask the kernels to publish per scan / join (servers do)
+    uint32_t seq = 0;               // batch number of the last launch
+    bool last_early = false;        // the last launch publishes per scan / join
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr, ev_fork = nullptr, ev_join = nullptr;
     // per-kernel timing of direct launches: scan kernel on the call's stream, join kernel on the side stream
     hipEvent_t ev_s0 = nullptr, ev_s1 = nullptr, ev_j0 = nullptr, ev_j1 = nullptr;
@@ -118,7 +131,14 @@ gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace
 std::string shape_bucket(const gace_request* reqs, uint32_t n);
 
 gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool use_graph);
-gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req);
+gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
+                            const std::vector<char>* done = nullptr);
+// Per-request completion (contexts with `early` set): writes the outputs of
+// each request of the running batch whose scan or join has published its
+// results and is not marked in `done` yet, marks it, and appends (request
+// index, status) to `out`.
+void collect_published(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, std::vector<char>& done,
+                       std::vector<std::pair<uint32_t, gace_status>>& out);
 gace_status run_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
                          hipStream_t st, bool use_graph);
 

@@ -6,8 +6,12 @@
 // slot is free and requests are waiting, it admits queued requests in arrival
 // order while their estimated workspace fits the slot, compiles them into one
 // batch and launches it, even while the other slots' batches are still running
-// (continuous batching).  Finished batches are detected by polling their done
-// events; each request's outputs and status are written and its waiter woken.
+// (continuous batching).  A request finishes as soon as its own scan or join
+// does: the kernels publish each finished scan's and join's results into the
+// slot's pinned result buffer and raise a host flag, which the worker polls;
+// the batch's done event finishes whatever has not published (scans with no
+// items, or every request after a device error).  Each request's outputs and
+// status are written once and its waiter woken.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -39,6 +43,8 @@ struct ServeSlot {
     std::vector<std::unique_ptr<OwnedRequest>> reqs;
     std::vector<gace_request> arr;
     std::vector<gace_status> per;
+    std::vector<char> fin;                                  // request finished before its batch
+    std::vector<std::pair<uint32_t, gace_status>> ready;    // requests finished by the last poll
     uint64_t ws = 0;
 };
 
@@ -96,29 +102,49 @@ struct gace_server {
     bool try_launch(ServeSlot& s, std::unique_lock<std::mutex>& lk);
 };
 
+// A running batch: requests whose scan or join has published its results
+// (per-request completion) are finished at once; the rest when the batch's
+// done event fires.
 bool gace_server::try_complete(ServeSlot& s, std::unique_lock<std::mutex>& lk) {
     if (!s.busy) return false;
     hipError_t q = hipEventQuery(s.ctx->ev_done);
-    if (q == hipErrorNotReady) return false;
+    if (q == hipErrorNotReady) {
+        s.ready.clear();
+        gace::collect_published(s.ctx, s.cb, s.arr.data(), s.fin, s.ready);
+        if (s.ready.empty()) return false;
+        const uint64_t t_done = now_ns();
+        for (const auto& rs : s.ready) {
+            TicketState& t = tickets[s.reqs[rs.first]->ticket];
+            t.done = true;
+            t.st = rs.second;
+            t.done_ns = t_done;
+        }
+        stats.completed += s.ready.size();
+        stats.completed_early += s.ready.size();
+        stats.inflight -= s.ready.size();
+        cv_done.notify_all();
+        return true;
+    }
     lk.unlock();
-    gace_status bst = GACE_OK;
     if (q == hipSuccess) {
-        bst = gace::finish_compiled(s.ctx, s.cb, s.arr.data(), s.per.data());
-        (void)bst;
+        (void)gace::finish_compiled(s.ctx, s.cb, s.arr.data(), s.per.data(), &s.fin);
     } else {
         for (auto& p : s.per) p = GACE_EDEVICE;
     }
     lk.lock();
     const uint64_t t_done = now_ns();
+    size_t n_late = 0;
     for (size_t i = 0; i < s.reqs.size(); ++i) {
+        if (s.fin[i]) continue;
         OwnedRequest& o = *s.reqs[i];
         TicketState& t = tickets[o.ticket];
         t.done = true;
         t.st = s.per[i];
         t.done_ns = t_done;
+        ++n_late;
     }
-    stats.completed += s.reqs.size();
-    stats.inflight -= s.reqs.size();
+    stats.completed += n_late;
+    stats.inflight -= n_late;
     stats.workspace_in_use -= s.ws;
     s.reqs.clear();
     s.arr.clear();
@@ -149,6 +175,7 @@ bool gace_server::try_launch(ServeSlot& s, std::unique_lock<std::mutex>& lk) {
     s.arr.clear();
     for (auto& o : s.reqs) s.arr.push_back(o->r);
     s.per.assign(s.arr.size(), GACE_OK);
+    s.fin.assign(s.arr.size(), 0);
     lk.unlock();
     gace::CompileOptions opt;
     opt.item_rows = s.ctx->sched.item_rows;
@@ -204,7 +231,7 @@ extern "C" {
 
 gace_status gace_server_create(int hip_device, const gace_server_cfg* cfg, gace_server** out) {
     if (!cfg || !out || cfg->max_inflight < 1 || cfg->max_inflight > 8 || cfg->max_batch < 1 ||
-        cfg->queue_capacity < 1) {
+        cfg->queue_capacity < 1 || (cfg->flags & ~GACE_SERVER_BATCH_COMPLETION)) {
         set_error("invalid server configuration");
         return GACE_EINVAL;
     }
@@ -215,6 +242,8 @@ gace_status gace_server_create(int hip_device, const gace_server_cfg* cfg, gace_
     srv->slots.resize(cfg->max_inflight);
     for (auto& s : srv->slots) {
         gace_status st = gace_create(hip_device, per, &s.ctx);
+        // requests finish as their scan or join does, unless asked otherwise
+        if (st == GACE_OK) s.ctx->early = !(cfg->flags & GACE_SERVER_BATCH_COMPLETION);
         if (st == GACE_OK && hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) {
             set_error("stream creation failed");
             st = GACE_EDEVICE;
@@ -303,14 +332,23 @@ gace_status gace_server_wait_times(gace_server* srv, uint64_t ticket, int64_t ti
         set_error("unknown ticket");
         return GACE_EINVAL;
     }
-    auto done = [&] { return srv->tickets[ticket].done; };
+    // the ticket may be collected by another waiter meanwhile: never re-create it
+    auto done = [&] {
+        auto t = srv->tickets.find(ticket);
+        return t == srv->tickets.end() || t->second.done;
+    };
     if (timeout_ns < 0) {
         srv->cv_done.wait(lk, done);
     } else if (!srv->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done)) {
         set_error("request still running");
         return GACE_ETIMEOUT;
     }
-    const TicketState& t = srv->tickets[ticket];
+    it = srv->tickets.find(ticket);
+    if (it == srv->tickets.end()) {
+        set_error("ticket already collected by another wait");
+        return GACE_EINVAL;
+    }
+    const TicketState& t = it->second;
     if (req_status) *req_status = t.st;
     if (submit_ns) *submit_ns = t.submit_ns;
     if (done_ns) *done_ns = t.done_ns;

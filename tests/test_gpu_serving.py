@@ -84,17 +84,56 @@ def test_served_results_equal_alone_and_oracle(env):
         g.gace_server_destroy(srv)
     assert not errors, errors
     assert stats["completed"] == len(order) and stats["batches"] >= 2
+    # requests finish as their own scan or join does
+    assert stats["completed_early"] > 0, stats
     for key in alone:
         st, res = served[key]
         assert st == 0, key
         assert res == alone[key], key
-    # and against the oracle for a sample of requests
-    for kind, i in order[:: max(1, len(order) // 12)]:
+    # and every request against the oracle
+    for kind, i in order:
         if kind == "sel":
             c, n, b = oracle.sel_request(w, i)
-            assert alone[(kind, i)] == (c.tolist(), n, b)
+            assert alone[(kind, i)] == (c.tolist(), n, b), (kind, i)
         else:
-            assert alone[(kind, i)] == oracle.join_request(w, i)
+            assert alone[(kind, i)] == oracle.join_request(w, i), (kind, i)
+
+
+def test_probe_finishes_before_the_join_in_its_batch(env):
+    """A small probe batched with a large join is done (results written, waiter
+    woken) before the join: completion is per request, not per batch."""
+    import torch
+    g, w, tabs, keys = env
+    dev = torch.device("cuda:0")
+    r, s = datagen.join_pair(40_000_000, 10_000_000, 2_000_000, 77, 41, 42)
+    kr = datagen.device_column(r.cols[0], r.n_rows, dev)
+    ks = datagen.device_column(s.cols[0], s.n_rows, dev)
+    big = [g.JoinRequest(g.Keys(kr, r.table_id, 5 + k, 1.0, 4096), g.Keys(ks, s.table_id, 6 + k, 1.0, 4096))
+           for k in range(2)]
+    kind, i = next(o for o in w.order if o[0] == "sel")
+    small = _req(g, w, tabs, keys, kind, i)
+    srv = g.gace_server_create(0, max_inflight=1, max_batch=64, queue_capacity=64, workspace_bytes=8 << 30)
+    try:
+        t_block = g.gace_server_submit(srv, big[0])        # occupies the only slot
+        import time
+        t_end = time.monotonic() + 30
+        while g.gace_server_stats_get(srv)["batches"] < 1 and time.monotonic() < t_end:
+            time.sleep(1e-4)
+        t_join = g.gace_server_submit(srv, big[1])         # these two queue behind it
+        t_small = g.gace_server_submit(srv, small)         # and form the next batch
+        st_s, _, done_s = g.gace_server_wait_times(srv, t_small, 60_000_000_000)
+        st_j, _, done_j = g.gace_server_wait_times(srv, t_join, 60_000_000_000)
+        st_b, _, _ = g.gace_server_wait_times(srv, t_block, 60_000_000_000)
+        stats = g.gace_server_stats_get(srv)
+    finally:
+        g.gace_server_destroy(srv)
+    assert (st_s, st_j, st_b) == (0, 0, 0)
+    assert stats["batches"] == 2, stats
+    assert done_s < done_j, (done_s, done_j)
+    c, n, b = oracle.sel_request(w, i)
+    assert _res(g, small) == (c.tolist(), n, b)
+    want = oracle.join_freq(kr.cpu().numpy(), r.table_id, 6, 1.0, 4096, ks.cpu().numpy(), s.table_id, 7, 1.0, 4096)
+    assert big[1].result() == want
 
 
 def test_server_rejects_invalid_and_oversized(env):
