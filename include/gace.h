@@ -271,6 +271,7 @@ typedef struct {
     uint64_t scan_alg_bytes, join_alg_bytes;
     uint32_t timed;
     float compile_ms;
+    uint64_t zones_skipped;   /* zones the batch's scans skipped by attached zone maps (gace_zone.h) */
 } gace_kernel_stats;
 
 gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out);

@@ -50,6 +50,23 @@ gace_status gace_probe_selectivity_zm(gace_ctx* ctx, const gace_table* table, co
                                       const gace_predicates* preds, const gace_sample_spec* spec, uint64_t* counts,
                                       gace_probe_info* info, uint64_t* zones_skipped, void* stream);
 
+/* Batched and served scans.  A zone map attached to a context is used by
+   every later gace_batch_run and gace_probe_selectivity on that context
+   whose table it matches (same row count, column addresses and types); one
+   attached to a server, by every later batch the server launches.  A shared
+   scan skips a zone only when no predicate of any request sharing the scan
+   can hold there, so every count equals the unpruned one.  The zone data
+   (skip bitmap and the scan's predicates, a few bytes per zone and 80 per
+   term) takes arena space after the batch's join tables; a batch where it
+   does not fit runs unpruned.  The zone map must stay alive while attached
+   (detach before gace_zonemap_destroy); attaching it again is a no-op.
+   gace_kernel_stats.zones_skipped reports the zones the last batch skipped.
+   Errors: GACE_EINVAL (NULL argument, zone map of another device, detach of
+   a map that is not attached). */
+gace_status gace_zonemap_attach(gace_ctx* ctx, const gace_zonemap* zm);
+gace_status gace_zonemap_detach(gace_ctx* ctx, const gace_zonemap* zm);
+gace_status gace_server_attach_zonemap(gace_server* srv, const gace_zonemap* zm);
+
 #ifdef __cplusplus
 }
 #endif

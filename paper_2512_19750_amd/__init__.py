@@ -99,7 +99,8 @@ class gace_trace_rec(ctypes.Structure):
 
 class gace_kernel_stats(ctypes.Structure):
     _fields_ = [("scan_ms", ctypes.c_double), ("join_ms", ctypes.c_double), ("scan_alg_bytes", ctypes.c_uint64),
-                ("join_alg_bytes", ctypes.c_uint64), ("timed", ctypes.c_uint32), ("compile_ms", ctypes.c_float)]
+                ("join_alg_bytes", ctypes.c_uint64), ("timed", ctypes.c_uint32), ("compile_ms", ctypes.c_float),
+                ("zones_skipped", ctypes.c_uint64)]
 
 
 class gace_server_cfg(ctypes.Structure):
@@ -185,7 +186,7 @@ ABI_FUNCTIONS = [
     "gace_estimate_selectivity", "gace_estimate_join",
     # gace_zone.h
     "gace_zonemap_build", "gace_zonemap_destroy", "gace_zonemap_info", "gace_zonemap_read",
-    "gace_probe_selectivity_zm",
+    "gace_probe_selectivity_zm", "gace_zonemap_attach", "gace_zonemap_detach", "gace_server_attach_zonemap",
     "gace_probe_selectivity_noalloc",
     "gace_read_ceiling",
 ]
@@ -271,6 +272,9 @@ def lib():
                                        ctypes.POINTER(gace_join_result), ctypes.POINTER(u32), P], i32),
             "gace_zonemap_build": ([P, ctypes.POINTER(gace_table), ctypes.POINTER(P), P], i32),
             "gace_zonemap_destroy": ([P], i32),
+            "gace_zonemap_attach": ([P, P], i32),
+            "gace_zonemap_detach": ([P, P], i32),
+            "gace_server_attach_zonemap": ([P, P], i32),
             "gace_zonemap_info": ([P, ctypes.POINTER(u64)], i32),
             "gace_zonemap_read": ([P, u32, P, P], i32),
             "gace_probe_selectivity_zm": ([P, ctypes.POINTER(gace_table), P, ctypes.POINTER(gace_predicates),
@@ -571,7 +575,8 @@ def gace_last_kernel_stats(ctx: int) -> dict:
     k = gace_kernel_stats()
     _check(lib().gace_last_kernel_stats(ctx, ctypes.byref(k)))
     return dict(timed=bool(k.timed), scan_ms=k.scan_ms, join_ms=k.join_ms, scan_alg_bytes=int(k.scan_alg_bytes),
-                join_alg_bytes=int(k.join_alg_bytes), compile_ms=float(k.compile_ms))
+                join_alg_bytes=int(k.join_alg_bytes), compile_ms=float(k.compile_ms),
+                zones_skipped=int(k.zones_skipped))
 
 
 def gace_set_graph(ctx: int, enable: bool = True):
@@ -921,6 +926,18 @@ def gace_zonemap_read(zm: int, col: int, dtype) -> Tuple[np.ndarray, np.ndarray]
     hi = np.zeros(max(n, 1), dtype=dtype)
     _check(lib().gace_zonemap_read(zm, col, lo.ctypes.data, hi.ctypes.data))
     return lo[:n], hi[:n]
+
+
+def gace_zonemap_attach(ctx: int, zm: int):
+    _check(lib().gace_zonemap_attach(ctx, zm))
+
+
+def gace_zonemap_detach(ctx: int, zm: int):
+    _check(lib().gace_zonemap_detach(ctx, zm))
+
+
+def gace_server_attach_zonemap(srv: int, zm: int):
+    _check(lib().gace_server_attach_zonemap(srv, zm))
 
 
 def gace_probe_selectivity_zm(ctx: int, table: Table, zm: int, preds, seed: int = 0, rate: float = 1.0,

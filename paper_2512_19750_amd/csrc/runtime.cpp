@@ -436,6 +436,7 @@ gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace
     if (cb.sel.empty() && cb.joins.empty()) return first;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "set device");
+    if (gace_status z = apply_zonemaps(c, cb, reqs, st)) return z;
     gace_status s = run_compiled(c, cb, reqs, per_req, st, use_graph);
     if (first == GACE_OK) first = s;
     return first;
@@ -726,6 +727,7 @@ gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out) {
     out->scan_alg_bytes = ctx->last_scan_bytes;
     out->join_alg_bytes = ctx->last_join_bytes;
     out->compile_ms = (float)ctx->last_compile_ms;
+    out->zones_skipped = zones_skipped_last(ctx);
     return GACE_OK;
 }
 

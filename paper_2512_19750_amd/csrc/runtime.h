@@ -62,6 +62,8 @@ const void* gace_kernel_handle(int which);
 
 using gace::TraceRec;
 
+struct gace_zonemap;
+
 struct gace_ctx {
     int device = 0;
     int n_cu = 0;
@@ -89,6 +91,11 @@ struct gace_ctx {
     bool early = false;             // ask the kernels to publish per scan / join (servers do)
     uint32_t seq = 0;               // batch number of the last launch
     bool last_early = false;        // the last launch publishes per scan / join
+    // zone maps attached for batched scans (not owned), and the last batch's
+    // skipped-zone counters (pinned, one per pruned scan)
+    std::vector<const gace_zonemap*> zonemaps;
+    const uint64_t* zm_counts = nullptr;
+    uint32_t zm_n_last = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr, ev_fork = nullptr, ev_join = nullptr;
     // per-kernel timing of direct launches: scan kernel on the call's stream, join kernel on the side stream
     hipEvent_t ev_s0 = nullptr, ev_s1 = nullptr, ev_j0 = nullptr, ev_j1 = nullptr;
@@ -139,6 +146,11 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
 // index, status) to `out`.
 void collect_published(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, std::vector<char>& done,
                        std::vector<std::pair<uint32_t, gace_status>>& out);
+// Zone pruning of a compiled batch's scans by the zone maps attached to c
+// (queued on st before the batch); and the zones the last batch skipped.
+gace_status apply_zonemaps(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, hipStream_t st);
+uint64_t zones_skipped_last(const gace_ctx* c);
+int zonemap_device(const gace_zonemap* zm);
 gace_status run_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, gace_status* per_req,
                          hipStream_t st, bool use_graph);
 

@@ -23,6 +23,7 @@
 #include <unordered_map>
 
 #include "runtime.h"
+#include "../../include/gace_zone.h"
 
 namespace {
 
@@ -96,6 +97,7 @@ struct gace_server {
     bool stop = false;
     std::thread worker;
     gace_server_stats stats{};
+    std::vector<const gace_zonemap*> zonemaps;   // attached zone maps, copied to a slot at each launch
 
     void run();
     bool try_complete(ServeSlot& s, std::unique_lock<std::mutex>& lk);
@@ -176,13 +178,15 @@ bool gace_server::try_launch(ServeSlot& s, std::unique_lock<std::mutex>& lk) {
     for (auto& o : s.reqs) s.arr.push_back(o->r);
     s.per.assign(s.arr.size(), GACE_OK);
     s.fin.assign(s.arr.size(), 0);
+    s.ctx->zonemaps = zonemaps;
     lk.unlock();
     gace::CompileOptions opt;
     opt.item_rows = s.ctx->sched.item_rows;
     opt.join_part_keys = s.ctx->sched.join_part_keys;
     opt.workers = (uint32_t)s.ctx->n_cu * s.ctx->sched.wgs_per_cu;
     gace::compile_batch(s.arr.data(), (uint32_t)s.arr.size(), opt, s.cb);
-    gace_status st = gace::launch_compiled(s.ctx, s.cb, s.stream, true);
+    gace_status st = gace::apply_zonemaps(s.ctx, s.cb, s.arr.data(), s.stream);
+    if (st == GACE_OK) st = gace::launch_compiled(s.ctx, s.cb, s.stream, true);
     lk.lock();
     if (st != GACE_OK) {
         const uint64_t t_done = now_ns();
@@ -353,6 +357,22 @@ gace_status gace_server_wait_times(gace_server* srv, uint64_t ticket, int64_t ti
     if (submit_ns) *submit_ns = t.submit_ns;
     if (done_ns) *done_ns = t.done_ns;
     srv->tickets.erase(ticket);
+    return GACE_OK;
+}
+
+gace_status gace_server_attach_zonemap(gace_server* srv, const gace_zonemap* zm) {
+    if (!srv || !zm) {
+        set_error("NULL argument");
+        return GACE_EINVAL;
+    }
+    if (gace::zonemap_device(zm) != srv->device) {
+        set_error("the zone map is on another device than the server");
+        return GACE_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(srv->mu);
+    for (const gace_zonemap* z : srv->zonemaps)
+        if (z == zm) return GACE_OK;
+    srv->zonemaps.push_back(zm);
     return GACE_OK;
 }
 

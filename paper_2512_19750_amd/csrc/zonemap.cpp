@@ -154,6 +154,155 @@ extern "C" gace_status gace_zonemap_read(const gace_zonemap* zm, uint32_t col, v
     return GACE_OK;
 }
 
+// ---------------------------------------------------------------- batches
+namespace gace {
+
+static bool zm_matches(const gace_zonemap* zm, const gace_table& t, int device) {
+    if (zm->n_rows != t.n_rows || zm->n_cols != t.n_cols || zm->device != device) return false;
+    for (uint32_t c = 0; c < t.n_cols; ++c)
+        if (zm->data[c] != t.cols[c].data || zm->dtype[c] != t.cols[c].dtype) return false;
+    return true;
+}
+
+// Zone pruning for the shared scans of a compiled batch.  For each scan on a
+// table with an attached zone map, the union of every predicate of every
+// request sharing the scan goes to the prune kernel, so a zone is skipped only
+// when no request of the scan can match in it.  The skip bitmaps, the staged
+// predicates and the skipped-zone counters sit in the arena after the joins'
+// per-item tables (the batch's static arena grows by their size); the plan's
+// scan descriptors get the bitmaps' addresses.  A batch whose zone data does
+// not fit the arena runs unpruned, with the same counts.
+gace_status apply_zonemaps(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs, hipStream_t st) {
+    c->zm_n_last = 0;
+    if (c->zonemaps.empty() || cb.scans.empty()) return GACE_OK;
+    std::vector<std::vector<uint32_t>> members(cb.scans.size());
+    for (const SelOut& so : cb.sel) members[so.scan].push_back(so.req);
+    struct Z {
+        uint32_t scan;
+        const gace_zonemap* zm;
+        uint64_t skip_off, terms_off, off_off;
+        uint32_t np, nt;
+    };
+    std::vector<Z> zs;
+    for (uint32_t s = 0; s < cb.scans.size(); ++s) {
+        if (members[s].empty()) continue;
+        const gace_table& t = reqs[members[s][0]].table;
+        for (const gace_zonemap* zm : c->zonemaps)
+            if (zm_matches(zm, t, c->device)) {
+                Z z{};
+                z.scan = s;
+                z.zm = zm;
+                for (uint32_t q : members[s]) {
+                    const gace_predicates& p = reqs[q].preds;
+                    z.np += p.n_preds;
+                    z.nt += p.n_preds ? p.pred_off[p.n_preds] : 0;
+                }
+                zs.push_back(z);
+                break;
+            }
+    }
+    if (zs.empty()) return GACE_OK;
+    // layout: counters (one u64 per zoned scan), then per scan its bitmap, terms and offsets
+    const uint64_t base = align256(cb.arena_static);
+    uint64_t at = base + align256(8 * zs.size());
+    for (Z& z : zs) {
+        z.skip_off = at;
+        at += align256((z.zm->n_zones + 31) / 32 * 4);
+        z.terms_off = at;
+        at += align256((uint64_t)std::max<uint32_t>(z.nt, 1) * sizeof(gace_term));
+        z.off_off = at;
+        at += align256(((uint64_t)z.np + 1) * 4);
+    }
+    if (at > c->arena_bytes) return GACE_OK;
+    const uint64_t up_b = at - base, down_off = align256(up_b);
+    const uint64_t h_need = down_off + 8 * zs.size();
+    if (c->h_hp_bytes < h_need) {
+        if (c->h_hp) (void)hipHostFree(c->h_hp);
+        c->h_hp = nullptr;
+        c->h_hp_bytes = 0;
+        ZTRY(hipHostMalloc((void**)&c->h_hp, h_need, hipHostMallocDefault), "pinned staging");
+        c->h_hp_bytes = h_need;
+    }
+    uint8_t* h = c->h_hp;
+    std::memset(h, 0, up_b);   // zero counters; the bitmaps are written whole by the kernel
+    for (Z& z : zs) {
+        gace_term* T = (gace_term*)(h + (z.terms_off - base));
+        uint32_t* O = (uint32_t*)(h + (z.off_off - base));
+        uint32_t nt = 0, np = 0;
+        O[0] = 0;
+        for (uint32_t q : members[z.scan]) {
+            const gace_predicates& p = reqs[q].preds;
+            const uint32_t pt = p.n_preds ? p.pred_off[p.n_preds] : 0;
+            if (pt) std::memcpy(T + nt, p.terms, (uint64_t)pt * sizeof(gace_term));
+            for (uint32_t i = 1; i <= p.n_preds; ++i) O[np + i] = nt + p.pred_off[i];
+            nt += pt;
+            np += p.n_preds;
+        }
+    }
+    ZTRY(hipMemcpyAsync(c->d_arena_base + base, h, up_b, hipMemcpyHostToDevice, st), "zone predicate upload");
+    PlanHdr H;
+    std::memcpy(&H, cb.plan.data(), sizeof(H));
+    ScanDesc* sd = (ScanDesc*)(cb.plan.data() + H.scans_off);
+    for (size_t i = 0; i < zs.size(); ++i) {
+        const Z& z = zs[i];
+        uint8_t* a = c->d_arena_base;
+        ZTRY(gace_launch_zone_prune(z.zm->d_mem + z.zm->zc_off, a + z.terms_off, (const uint32_t*)(a + z.off_off),
+                                    z.np, z.zm->n_zones, (uint32_t*)(a + z.skip_off), a + base + 8 * i, st),
+             "zone prune kernel");
+        sd[z.scan].zskip = (uint64_t)(uintptr_t)(a + z.skip_off);
+        sd[z.scan].n_zones = z.zm->n_zones;
+        cb.scans[z.scan].zskip = sd[z.scan].zskip;
+        cb.scans[z.scan].n_zones = sd[z.scan].n_zones;
+    }
+    ZTRY(hipMemcpyAsync(h + down_off, c->d_arena_base + base, 8 * zs.size(), hipMemcpyDeviceToHost, st),
+         "zone counter download");
+    c->zm_counts = (const uint64_t*)(h + down_off);
+    c->zm_n_last = (uint32_t)zs.size();
+    cb.arena_static = at;
+    H.arena_static = at;
+    std::memcpy(cb.plan.data(), &H, sizeof(H));
+    return GACE_OK;
+}
+
+int zonemap_device(const gace_zonemap* zm) { return zm->device; }
+
+uint64_t zones_skipped_last(const gace_ctx* c) {
+    uint64_t n = 0;
+    for (uint32_t i = 0; i < c->zm_n_last; ++i) n += c->zm_counts[i];
+    return n;
+}
+
+}  // namespace gace
+
+extern "C" gace_status gace_zonemap_attach(gace_ctx* ctx, const gace_zonemap* zm) {
+    if (!ctx || !zm) {
+        set_error("NULL argument");
+        return GACE_EINVAL;
+    }
+    if (zm->device != ctx->device) {
+        set_error("the zone map is on another device than the context");
+        return GACE_EINVAL;
+    }
+    for (const gace_zonemap* z : ctx->zonemaps)
+        if (z == zm) return GACE_OK;
+    ctx->zonemaps.push_back(zm);
+    return GACE_OK;
+}
+
+extern "C" gace_status gace_zonemap_detach(gace_ctx* ctx, const gace_zonemap* zm) {
+    if (!ctx || !zm) {
+        set_error("NULL argument");
+        return GACE_EINVAL;
+    }
+    for (size_t i = 0; i < ctx->zonemaps.size(); ++i)
+        if (ctx->zonemaps[i] == zm) {
+            ctx->zonemaps.erase(ctx->zonemaps.begin() + (long)i);
+            return GACE_OK;
+        }
+    set_error("zone map not attached to this context");
+    return GACE_EINVAL;
+}
+
 extern "C" gace_status gace_probe_selectivity_zm(gace_ctx* ctx, const gace_table* table, const gace_zonemap* zm,
                                                  const gace_predicates* preds, const gace_sample_spec* spec,
                                                  uint64_t* counts, gace_probe_info* info, uint64_t* zones_skipped,

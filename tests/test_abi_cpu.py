@@ -46,7 +46,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(g.gace_join_result) == 72
     assert ctypes.sizeof(g.gace_schedule) == 32
     assert [f for f, _ in g.gace_schedule._fields_][-2] == "agg_wgs_per_cu"
-    assert ctypes.sizeof(g.gace_kernel_stats) == 40
+    assert ctypes.sizeof(g.gace_kernel_stats) == 48
 
 
 def test_version(L):
@@ -119,3 +119,22 @@ def test_check_join(L):
     assert g.gace_check_request(mis) == g.GACE_EINVAL
     null = g.JoinRequest(g.Keys(K(0, 10), 1), g.Keys(K(0x2000, 10), 2))
     assert g.gace_check_request(null) == g.GACE_EINVAL
+
+
+def test_struct_sizes_match_the_c_headers(tmp_path):
+    """Every ctypes mirror has the size the C compiler gives the header's struct."""
+    import subprocess
+    names = ["gace_term", "gace_column", "gace_table", "gace_sample_spec", "gace_keys", "gace_join_result",
+             "gace_request", "gace_probe_info", "gace_schedule", "gace_kernel_stats", "gace_server_cfg",
+             "gace_server_stats"]
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "gace.h"\n#include "gace_zone.h"\nint main(void) {\n' +
+                   "".join('    printf("%%s %%zu\\n", "%s", sizeof(%s));\n' % (n, n) for n in names) +
+                   "    return 0;\n}\n")
+    exe = tmp_path / "sizes"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    c_sizes = dict(zip(out[::2], (int(x) for x in out[1::2])))
+    for n in names:
+        assert ctypes.sizeof(getattr(g, n)) == c_sizes[n], n
