@@ -177,7 +177,8 @@ typedef struct {
     uint32_t wg_threads;       /* 256 or 512 */
     uint32_t wgs_per_cu;       /* scan kernel grid = CUs * wgs_per_cu (CUs * 1 in batches with joins) */
     uint32_t item_rows;        /* target sampled rows per work item */
-    uint32_t count_mode;       /* 0 auto, 1 ballot, 2 transpose */
+    uint32_t count_mode;       /* 0 auto (ballot for <= 6 active predicates, else 2), 1 ballot,
+                                  2 carry-save adder tree over 16 rows + a wave transpose per bit plane */
     uint32_t join_part_keys;   /* expected sampled keys per join hash partition (power of two) */
     uint32_t join_wgs_per_cu;  /* join partitioning kernel grid = CUs * join_wgs_per_cu */
     uint32_t agg_wgs_per_cu;   /* join aggregation kernel grid = CUs * agg_wgs_per_cu */

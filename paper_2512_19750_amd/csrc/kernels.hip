@@ -62,7 +62,7 @@ struct BatchArgs {
     JoinAcc* accs;
     uint8_t* arena_base;       // join tables and partition buffers
     Arena* arena;
-    uint32_t count_mode;       // 0 auto, 1 ballot, 2 transpose
+    uint32_t count_mode;       // 0 auto, 1 ballot, 2 adder tree + transpose per bit plane
     uint32_t agg_slots;        // aggregation kernel: LDS table slots (power of two)
     TraceRec* trace;           // one record per item when the plan asks for tracing
     uint64_t spin_limit;       // polls before a join's phase wait gives up (0: at once)
@@ -207,21 +207,72 @@ __device__ __forceinline__ void transpose64(uint32_t& lo, uint32_t& hi, int lane
 #undef GACE_TSTAGE
 }
 
-// add the 64 rows' bits to the per-lane counter (lane p counts predicate p)
-__device__ __forceinline__ void count_rows(uint64_t m, uint64_t active, uint32_t& cnt, int lane, uint32_t mode) {
-    const int na = __popcll(active);
-    if (mode == 1 || (mode == 0 && na <= 6)) {
-        uint64_t a = active;
-        while (a) {
-            const int p = __ffsll((long long)a) - 1;
-            a &= a - 1;
-            const uint32_t c = (uint32_t)__popcll(__ballot((m >> p) & 1ull));
-            if (lane == p) cnt += c;
-        }
-    } else {
-        uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+// ballot count of one row slot: for each active predicate p, the number of
+// the wave's 64 rows (one per lane) whose bit p is set goes to lane p
+__device__ __forceinline__ void count_ballot(uint64_t m, uint64_t active, uint32_t& cnt, int lane) {
+    uint64_t a = active;
+    while (a) {
+        const int p = __ffsll((long long)a) - 1;
+        a &= a - 1;
+        const uint32_t c = (uint32_t)__popcll(__ballot((m >> p) & 1ull));
+        if (lane == p) cnt += c;
+    }
+}
+
+// a + b + c at every bit position: carry (weight 2) and sum (weight 1) words
+__device__ __forceinline__ void csa(uint64_t& carry, uint64_t& sum, uint64_t a, uint64_t b, uint64_t c) {
+    const uint64_t u = a ^ b;
+    carry = (a & b) | (u & c);
+    sum = u ^ c;
+}
+
+// The lane's 16 row masks summed at every bit position into a 5-bit count,
+// bit plane p[k] of weight 2^k, by a carry-save adder tree: 11 full and 4
+// half adders, 63 word operations for 16 rows.
+__device__ __forceinline__ void add16(const uint64_t (&d)[16], uint64_t (&p)[5]) {
+    uint64_t c2[8], s1[5], t1[2];
+    csa(c2[0], s1[0], d[0], d[1], d[2]);
+    csa(c2[1], s1[1], d[3], d[4], d[5]);
+    csa(c2[2], s1[2], d[6], d[7], d[8]);
+    csa(c2[3], s1[3], d[9], d[10], d[11]);
+    csa(c2[4], s1[4], d[12], d[13], d[14]);
+    csa(c2[5], t1[0], s1[0], s1[1], s1[2]);
+    csa(c2[6], t1[1], s1[3], s1[4], d[15]);
+    p[0] = t1[0] ^ t1[1];
+    c2[7] = t1[0] & t1[1];
+    uint64_t c4[4], s2[3];
+    csa(c4[0], s2[0], c2[0], c2[1], c2[2]);
+    csa(c4[1], s2[1], c2[3], c2[4], c2[5]);
+    csa(c4[2], s2[2], s2[0], s2[1], c2[6]);
+    p[1] = s2[2] ^ c2[7];
+    c4[3] = s2[2] & c2[7];
+    uint64_t c8[2], s4;
+    csa(c8[0], s4, c4[0], c4[1], c4[2]);
+    p[2] = s4 ^ c4[3];
+    c8[1] = s4 & c4[3];
+    p[3] = c8[0] ^ c8[1];
+    p[4] = c8[0] & c8[1];
+}
+
+// a tile's 16 row masks per lane (rows out of range already 0) added to the
+// per-lane counters (lane p counts predicate p).  Ballot per active predicate
+// for few of them (mode 1, or mode 0 with at most 6); else (mode 2, or mode
+// 0) the adder tree, then one 64x64 wave transpose per bit plane: 5
+// transposes per 16 rows instead of one per row.
+__device__ __forceinline__ void count_tile(const uint64_t (&d)[16], uint64_t active, uint32_t& cnt, int lane,
+                                           uint32_t mode) {
+    if (mode == 1 || (mode == 0 && __popcll(active) <= 6)) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) count_ballot(d[i], active, cnt, lane);
+        return;
+    }
+    uint64_t p[5];
+    add16(d, p);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        uint32_t lo = (uint32_t)p[k], hi = (uint32_t)(p[k] >> 32);
         transpose64(lo, hi, lane);
-        cnt += (uint32_t)(__popc(lo) + __popc(hi));
+        cnt += (uint32_t)(__popc(lo) + __popc(hi)) << k;
     }
 }
 
@@ -423,8 +474,10 @@ __device__ __forceinline__ uint32_t scan_blocks(const GACE_CONST ColProg* cols, 
         for (int j = 0; j < kQuads; ++j) {
             const uint64_t rq = q0 + 256ull * j;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) count_rows(rq + u < r1 ? m[4 * j + u] : 0ull, active, cnt, lane, mode);
+            for (int u = 0; u < 4; ++u)
+                if (rq + u >= r1) m[4 * j + u] = 0ull;
         }
+        count_tile(m, active, cnt, lane, mode);
     };
 
     // ---- full tiles, pipelined over (tile, column) units
@@ -544,8 +597,7 @@ __device__ __forceinline__ void fine_group(const GACE_CONST ColProg* cols, const
             lookup32<AS>(P, tab, v, m);
         }
     }
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) count_rows(m[i], active, cnt, lane, mode);
+    count_tile(m, active, cnt, lane, mode);
 }
 
 __device__ __forceinline__ void scan_fine(const BatchArgs& a, const ScanDesc& S, const GACE_CONST GroupDesc* groups,
