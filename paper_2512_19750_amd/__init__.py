@@ -492,6 +492,34 @@ def gace_probe_selectivity(ctx: int, table: Table, preds, seed: int = 0, rate: f
     return counts[:len(preds)], int(info.sampled_rows), int(info.kept_blocks)
 
 
+class PreparedProbe:
+    """One selectivity probe marshalled once (table, predicates, sampling spec,
+    output arrays), so repeated calls go straight to the C ABI: the latency
+    of a call is then the library's, not the binding's."""
+
+    def __init__(self, table: Table, preds, seed: int = 0, rate: float = 1.0, block_rows: int = 4096):
+        self._keep = _Keep()
+        self.t = _make_table(table, self._keep)
+        self.p = _make_preds(preds, [_dtype_code(c) for c in table.cols], self._keep)
+        self.s = _make_spec(seed, rate, block_rows)
+        self.n = len(preds)
+        self.counts = np.zeros(max(self.n, 1), dtype=np.uint64)
+        self.info = gace_probe_info()
+        self._cptr = self.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+    def run(self, ctx: int, stream=None):
+        """gace_probe_selectivity -> (counts, sampled_rows, kept_blocks); counts is reused by the next call"""
+        _check(lib().gace_probe_selectivity(ctx, ctypes.byref(self.t), ctypes.byref(self.p), ctypes.byref(self.s),
+                                            self._cptr, ctypes.byref(self.info), _stream_handle(stream)))
+        return self.counts[:self.n], int(self.info.sampled_rows), int(self.info.kept_blocks)
+
+    def run_noalloc(self, stream=None):
+        """gace_probe_selectivity_noalloc, same results"""
+        _check(lib().gace_probe_selectivity_noalloc(ctypes.byref(self.t), ctypes.byref(self.p), ctypes.byref(self.s),
+                                                    self._cptr, ctypes.byref(self.info), _stream_handle(stream)))
+        return self.counts[:self.n], int(self.info.sampled_rows), int(self.info.kept_blocks)
+
+
 def gace_probe_selectivity_noalloc(table: Table, preds, seed: int = 0, rate: float = 1.0,
                                    block_rows: int = 4096, stream=None, counts=None):
     """As gace_probe_selectivity, on the current device, with the library's

@@ -788,15 +788,20 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         return S.n_req == 1 && S.log2B < kZoneLog2 && S.thr_max > (1ull << (S.log2B + 20));
     };
     // a small batch (a single probe, a short served batch) still gets about
-    // four items per worker, down to items of 4096 rows; the rows an item
-    // reads are its kept rows, or all its rows for the row-by-row scan
+    // four items per worker, down to items of 1024 expected kept rows: in a
+    // sparse sample (1 % of 4096-row blocks) an item then spans ~25 blocks and
+    // holds a kept block one time in four, so the work queue spreads the
+    // kept tiles about one per workgroup instead of stacking several in one
+    // item (an item with no kept block costs one sampling decision); the
+    // rows an item reads are its kept rows, or all its rows for the
+    // row-by-row scan
     uint32_t item_rows = opt.item_rows;
     if (opt.workers) {
         double rows_read = 0.0;
         for (const ScanDesc& S : scans)
             rows_read += (double)S.n_rows *
                          (is_fine(S) || S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0);
-        const double cap = std::max(4096.0, rows_read / (4.0 * opt.workers));
+        const double cap = std::max(1024.0, rows_read / (4.0 * opt.workers));
         if (cap < item_rows) item_rows = (uint32_t)cap;
     }
     for (uint32_t s = 0; s < scans.size(); ++s) {

@@ -70,6 +70,12 @@ struct BatchArgs {
     uint32_t* host_flags;      // device address of the pinned completion flags
 };
 
+// the batch's work items: in the plan buffer after the descriptors when they
+// fit there (one upload), else in their own region
+__device__ __forceinline__ const Item* batch_items(const BatchArgs& a, const PlanHdr& H) {
+    return H.items_off ? (const Item*)(a.plan + H.items_off) : a.items;
+}
+
 // relaxed device-scope read of a value other workgroups updated with atomics
 __device__ __forceinline__ unsigned long long load_agent(const unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1821,7 +1827,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 8))
         const uint32_t idx = pop_item(&a.head[0], 0, &s_item);
         if (idx >= H.n_scan_items) break;
         const uint64_t t0 = (uint64_t)wall_clock64();
-        const Item it = a.items[idx];
+        const Item it = batch_items(a, H)[idx];
         scan_item(a, H, it, lds);
         worked = true;
         __syncthreads();
@@ -1859,7 +1865,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))
         if (idx >= H.n_join_end) break;
         const uint64_t t0 = (uint64_t)wall_clock64();
         uint64_t t1 = t0, work = 0;
-        const Item it = a.items[idx];
+        const Item it = batch_items(a, H)[idx];
         const JoinDesc* jd = (const JoinDesc*)(a.plan + H.joins_off) + it.idx;
         JoinAcc& acc = a.accs[jd->acc];
         switch (it.kind) {
@@ -1914,7 +1920,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))
         if (idx >= H.n_items) break;
         const uint64_t t0 = (uint64_t)wall_clock64();
         uint64_t work = 0;
-        const Item it = a.items[idx];
+        const Item it = batch_items(a, H)[idx];
         const JoinDesc* jd = (const JoinDesc*)(a.plan + H.joins_off) + it.idx;
         jagg_item(a, jd, it, lds, work);
         __syncthreads();
@@ -1940,6 +1946,24 @@ __global__ void __launch_bounds__(kWG) gace_init_kernel(const uint8_t* plan, uin
         head[2] = 0;
         arena->used = H.arena_static;
     }
+}
+
+// After a batch: its counters, histograms and join accumulators copied into
+// the pinned host result buffer (one small kernel instead of three copies;
+// the launch boundary orders it after the batch's kernels)
+__global__ void __launch_bounds__(kWG) gace_publish_kernel(const uint8_t* plan, const unsigned long long* counts,
+                                                           const unsigned long long* hist, const JoinAcc* accs,
+                                                           uint8_t* host_res) {
+    const PlanHdr H = *(const PlanHdr*)plan;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long* hc = (unsigned long long*)host_res;
+    unsigned long long* hh = (unsigned long long*)(host_res + kHostHistOff);
+    unsigned long long* ha = (unsigned long long*)(host_res + kHostAccsOff);
+    for (uint64_t i = tid; i < H.n_counts; i += stride) hc[i] = counts[i];
+    for (uint64_t i = tid; i < H.n_hist; i += stride) hh[i] = hist[i];
+    const uint64_t na = (uint64_t)H.n_joins * (sizeof(JoinAcc) / 8);
+    for (uint64_t i = tid; i < na; i += stride) ha[i] = ((const unsigned long long*)accs)[i];
 }
 
 // Kept-block bit mask for a host-resident table: bit (b mod 32) of word b / 32
@@ -2197,6 +2221,15 @@ hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hi
     hipLaunchKernelGGL(gace::gace_init_kernel, dim3(256), dim3(gace::kWG), 0, stream, (const uint8_t*)plan,
                        (uint32_t*)head, (unsigned long long*)counts, (unsigned long long*)hist,
                        (gace::JoinAcc*)accs, (gace::Arena*)arena);
+    return hipGetLastError();
+}
+
+hipError_t gace_launch_publish(const void* plan, const void* counts, const void* hist, const void* accs,
+                               void* host_res, uint32_t grid, hipStream_t stream) {
+    (void)hipGetLastError();   // report this launch's error, not an earlier call's
+    hipLaunchKernelGGL(gace::gace_publish_kernel, dim3(grid), dim3(gace::kWG), 0, stream, (const uint8_t*)plan,
+                       (const unsigned long long*)counts, (const unsigned long long*)hist,
+                       (const gace::JoinAcc*)accs, (uint8_t*)host_res);
     return hipGetLastError();
 }
 

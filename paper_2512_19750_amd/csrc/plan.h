@@ -52,7 +52,7 @@ struct PlanHdr {
     uint32_t early;          // nonzero: the scans and each join publish their results to the host when done
     uint32_t seq;            // ... raising their host flags to this batch number
     uint32_t wg_done_off;    // hist entry counting the scan kernel's finished workgroups
-    uint32_t reserved;
+    uint32_t items_off;      // byte offset of the work items in the plan buffer (0: in their own region)
 };
 
 // Per-request completion.  When a plan asks for it, the last workgroup of

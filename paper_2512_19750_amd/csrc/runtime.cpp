@@ -247,10 +247,19 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     if (++c->seq == 0) ++c->seq;
     hs->early = c->last_early ? 1u : 0u;
     hs->seq = c->seq;
-    std::memcpy(c->h_stage + kPlanCap, cb.items.data(), items_b);
-    HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, plan_b, hipMemcpyHostToDevice, st), "plan upload");
-    if (items_b)
+    // the items follow the plan in one upload when both fit the plan region
+    const uint64_t items_at = (plan_b + 15) / 16 * 16;
+    if (items_at + items_b <= kPlanCap) {
+        hs->items_off = items_b ? (uint32_t)items_at : 0u;
+        std::memcpy(c->h_stage + items_at, cb.items.data(), items_b);
+        HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, items_b ? items_at + items_b : plan_b, hipMemcpyHostToDevice,
+                               st), "plan upload");
+    } else {
+        hs->items_off = 0;
+        std::memcpy(c->h_stage + kPlanCap, cb.items.data(), items_b);
+        HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, plan_b, hipMemcpyHostToDevice, st), "plan upload");
         HIP_TRY(hipMemcpyAsync(c->d_items, c->h_stage + kPlanCap, items_b, hipMemcpyHostToDevice, st), "item upload");
+    }
     HIP_TRY(hipEventRecord(c->ev0, st), "batch start event");
     const bool beside = scan_beside_joins(cb);
     if (use_graph) {
@@ -264,14 +273,24 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
         c->last_timed = true;
     }
     HIP_TRY(hipEventRecord(c->ev1, st), "batch end event");
-    uint8_t* hc = c->h_result;
-    uint8_t* hh = hc + kCountsCap;
-    uint8_t* ha = hh + kHistCap;
-    if (cb.n_counts)
-        HIP_TRY(hipMemcpyAsync(hc, c->d_counts, cb.n_counts * 8ull, hipMemcpyDeviceToHost, st), "counts download");
-    if (cb.n_hist)
-        HIP_TRY(hipMemcpyAsync(hh, c->d_hist, cb.n_hist * 8ull, hipMemcpyDeviceToHost, st), "hist download");
-    if (accs_b) HIP_TRY(hipMemcpyAsync(ha, c->d_accs, accs_b, hipMemcpyDeviceToHost, st), "join download");
+    // results to the pinned buffer: one small kernel writing host memory, or
+    // (without a device address for it) one copy per region
+    const uint64_t words = cb.n_counts + cb.n_hist + accs_b / 8;
+    if (c->d_host_res && words) {
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(64, (words + 4095) / 4096);
+        HIP_TRY(gace_launch_publish(c->d_plan, c->d_counts, c->d_hist, c->d_accs, c->d_host_res, grid, st),
+                "result publish kernel");
+    } else {
+        uint8_t* hc = c->h_result;
+        uint8_t* hh = hc + kCountsCap;
+        uint8_t* ha = hh + kHistCap;
+        if (cb.n_counts)
+            HIP_TRY(hipMemcpyAsync(hc, c->d_counts, cb.n_counts * 8ull, hipMemcpyDeviceToHost, st),
+                    "counts download");
+        if (cb.n_hist)
+            HIP_TRY(hipMemcpyAsync(hh, c->d_hist, cb.n_hist * 8ull, hipMemcpyDeviceToHost, st), "hist download");
+        if (accs_b) HIP_TRY(hipMemcpyAsync(ha, c->d_accs, accs_b, hipMemcpyDeviceToHost, st), "join download");
+    }
     if (c->trace) {
         c->last_trace.resize(cb.items.size());
         if (!cb.items.empty())

@@ -57,6 +57,8 @@ hipError_t gace_launch_join(const void* args, uint32_t grid, int beside_scan, hi
 hipError_t gace_launch_agg(const void* args, uint32_t grid, hipStream_t stream);
 hipError_t gace_launch_read(const void* p, uint64_t n16, void* sink, hipStream_t stream);
 const void* gace_kernel_handle(int which);
+hipError_t gace_launch_publish(const void* plan, const void* counts, const void* hist, const void* accs,
+                               void* host_res, uint32_t grid, hipStream_t stream);
 }
 
 
