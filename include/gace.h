@@ -231,7 +231,9 @@ gace_status gace_probe_selectivity_noalloc(const gace_table* table, const gace_p
                                            void* stream);
 
 /* ---------------------------------------------------------------- batched path */
-/* Run n requests of either kind in one persistent, graph-replayed launch.
+/* Run n requests of either kind in one launch of the persistent kernels: the
+   scan kernel and the join stage run concurrently, each replayed from its
+   captured graph.
    Selectivity requests on the same table, seed and block size share one
    scan (their samples are nested by rate).  per_req (n entries, may be NULL)
    receives each request's status; an invalid request fails alone.  Returns
@@ -262,9 +264,9 @@ gace_status gace_last_batch_stats(gace_ctx* ctx, double* kernel_ms, uint64_t* al
    stream where it runs concurrently; with the algorithmic HBM bytes of each
    (scan: kept rows x referenced column widths per shared scan; join: 8 bytes
    per sampled key + 16 bytes per distinct key and side).
-   Both launch modes time the kernels: a captured graph holds the same
-   timing events as event record nodes around its kernel nodes (timed = 1
-   once a batch ran).  compile_ms is
+   Both launch modes time the kernels: graph replay captures one graph per
+   branch (the scan kernel; the join stage) and records the same timing
+   events around each graph launch (timed = 1 once a batch ran).  compile_ms is
    the host time spent validating and compiling the batch's requests into
    the device plan (either launch mode). */
 typedef struct {
@@ -278,7 +280,7 @@ typedef struct {
 gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out);
 
 /* Select how gace_batch_run launches: graph replay (enable != 0, the
-   default) or direct launches with per-kernel timing events.  Results are
+   default) or direct launches.  Both time each kernel branch; results are
    identical. */
 gace_status gace_set_graph(gace_ctx* ctx, int enable);
 

@@ -101,36 +101,6 @@ static uint32_t scan_grid(gace_ctx* c, bool beside) {
 static uint32_t join_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.join_wgs_per_cu; }
 static uint32_t agg_grid(gace_ctx* c) { return (uint32_t)c->n_cu * c->sched.agg_wgs_per_cu; }
 
-// init kernel, then the scan kernel on st and the join kernel on the side
-// stream concurrently (they touch disjoint state), joined back into st.
-// The kernels a batch has no items for are left out: a single selectivity
-// probe is init + scan on one stream.
-static gace_status launch_direct(gace_ctx* c, hipStream_t st, hipStream_t side, bool timed, bool scans, bool joins,
-                                 bool beside) {
-    BatchArgsHost a = make_args(c);
-    HIP_TRY(gace_launch_init(c->d_plan, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st), "init kernel");
-    if (joins) {
-        HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
-        HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
-        if (timed) HIP_TRY(hipEventRecord(c->ev_j0, side), "join start event");
-        // the join kernel's smaller-tile variant leaves room on each CU for
-        // the scan kernel's workgroup
-        HIP_TRY(gace_launch_join(&a, join_grid(c), beside ? 1 : 0, side), "join kernel");
-        HIP_TRY(gace_launch_agg(&a, agg_grid(c), side), "aggregation kernel");
-        if (timed) HIP_TRY(hipEventRecord(c->ev_j1, side), "join end event");
-    }
-    if (scans) {
-        if (timed) HIP_TRY(hipEventRecord(c->ev_s0, st), "scan start event");
-        HIP_TRY(gace_launch_scan(&a, scan_grid(c, beside), st), "scan kernel");
-        if (timed) HIP_TRY(hipEventRecord(c->ev_s1, st), "scan end event");
-    }
-    if (joins) {
-        HIP_TRY(hipEventRecord(c->ev_join, side), "join event");
-        HIP_TRY(hipStreamWaitEvent(st, c->ev_join, 0), "join wait");
-    }
-    return GACE_OK;
-}
-
 static void drop_graph(gace_ctx* c, int k) {
     if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
     if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
@@ -142,64 +112,33 @@ static void drop_graph(gace_ctx* c) {
     for (int k = 0; k < 8; ++k) drop_graph(c, k);
 }
 
-// Brackets the kernel nodes first .. last of a captured graph with event
-// record nodes for e0 (before first, after first's dependencies) and e1
-// (after last), so a replay times them as the direct launch's events do.
-static gace_status bracket_nodes(hipGraph_t g, hipGraphNode_t first, hipGraphNode_t last, hipEvent_t e0,
-                                 hipEvent_t e1) {
-    size_t nd = 0;
-    HIP_TRY(hipGraphNodeGetDependencies(first, nullptr, &nd), "graph node dependencies");
-    std::vector<hipGraphNode_t> deps(nd);
-    if (nd) HIP_TRY(hipGraphNodeGetDependencies(first, deps.data(), &nd), "graph node dependencies");
-    hipGraphNode_t r0 = nullptr, r1 = nullptr;
-    HIP_TRY(hipGraphAddEventRecordNode(&r0, g, deps.data(), nd, e0), "graph event node");
-    HIP_TRY(hipGraphAddDependencies(g, &r0, &first, 1), "graph dependency");
-    HIP_TRY(hipGraphAddEventRecordNode(&r1, g, &last, 1, e1), "graph event node");
-    return GACE_OK;
-}
-
-// Adds the per-kernel timing events to a captured batch graph: the scan
-// kernel between ev_s0 and ev_s1, the join stage (partitioning kernel, then
-// aggregation kernel) between ev_j0 and ev_j1.  Kernel nodes are found by
-// the kernels' host-side handles.
-static gace_status add_timing_nodes(gace_ctx* c, hipGraph_t g, bool& timed) {
-    size_t n = 0;
-    HIP_TRY(hipGraphGetNodes(g, nullptr, &n), "graph nodes");
-    std::vector<hipGraphNode_t> nodes(n);
-    if (n) HIP_TRY(hipGraphGetNodes(g, nodes.data(), &n), "graph nodes");
-    const void* h_scan = gace_kernel_handle(0);
-    const void* h_join[2] = {gace_kernel_handle(1), gace_kernel_handle(2)};
-    const void* h_agg = gace_kernel_handle(3);
-    hipGraphNode_t scan = nullptr, join = nullptr, agg = nullptr;
-    int n_kernels = 0;
-    for (hipGraphNode_t nd : nodes) {
-        hipGraphNodeType t;
-        HIP_TRY(hipGraphNodeGetType(nd, &t), "graph node type");
-        if (t != hipGraphNodeTypeKernel) continue;
-        ++n_kernels;
-        hipKernelNodeParams p;
-        HIP_TRY(hipGraphKernelNodeGetParams(nd, &p), "graph kernel node");
-        if (p.func == h_scan) scan = nd;
-        else if (p.func == h_join[0] || p.func == h_join[1]) join = nd;
-        else if (p.func == h_agg) agg = nd;
+// The kernels of one branch of a batch: the scan kernel (branch 0, or 1 when
+// it runs beside the joins) or the join stage, partitioning then aggregation
+// (branch 2, or 3 beside a scan).
+static gace_status launch_branch(gace_ctx* c, int k, hipStream_t s) {
+    BatchArgsHost a = make_args(c);
+    if (k < 2) {
+        HIP_TRY(gace_launch_scan(&a, scan_grid(c, k == 1), s), "scan kernel");
+    } else {
+        // the join kernel's smaller-tile variant leaves room on each CU for
+        // the scan kernel's workgroup
+        HIP_TRY(gace_launch_join(&a, join_grid(c), k == 3 ? 1 : 0, s), "join kernel");
+        HIP_TRY(gace_launch_agg(&a, agg_grid(c), s), "aggregation kernel");
     }
-    // init kernel + scan and / or join + aggregation: every kernel identified
-    timed = n_kernels == 1 + (scan ? 1 : 0) + (join ? 1 : 0) + (agg ? 1 : 0) && (join != nullptr) == (agg != nullptr);
-    if (!timed) return GACE_OK;
-    if (scan)
-        if (gace_status s = bracket_nodes(g, scan, scan, c->ev_s0, c->ev_s1)) return s;
-    if (join)
-        if (gace_status s = bracket_nodes(g, join, agg, c->ev_j0, c->ev_j1)) return s;
     return GACE_OK;
 }
 
-// the graph of batch kind k ((scan beside the joins << 2) | (has scans << 1) | has joins) for the
-// current schedule
+// The captured graph of branch k for the current schedule.  A batch replays
+// one graph per branch rather than one graph of the whole batch, so that the
+// timing events stay ordinary records on the branch's stream around the
+// graph launch: event-record nodes added to a captured graph kept the
+// context's workspace allocated after gace_destroy (measured: hipFree
+// returned success and the memory never came back).
 static gace_status ensure_graph(gace_ctx* c, int k) {
     if (c->graph_exec[k] && std::memcmp(&c->graph_sched[k], &c->sched, sizeof(gace_schedule)) == 0) return GACE_OK;
     drop_graph(c, k);
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    gace_status st = launch_direct(c, c->cap_stream, c->cap_side, false, (k & 2) != 0, (k & 1) != 0, (k & 4) != 0);
+    gace_status st = launch_branch(c, k, c->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (st != GACE_OK) {
@@ -208,14 +147,42 @@ static gace_status ensure_graph(gace_ctx* c, int k) {
     }
     if (e != hipSuccess) return hip_fail(e, "end capture");
     c->graph[k] = g;
-    bool timed = false;
-    if (gace_status s = add_timing_nodes(c, g, timed)) {
-        drop_graph(c, k);
-        return s;
-    }
-    c->graph_timed[k] = timed;
     HIP_TRY(hipGraphInstantiate(&c->graph_exec[k], g, nullptr, nullptr, 0), "graph instantiate");
     c->graph_sched[k] = c->sched;
+    return GACE_OK;
+}
+
+static gace_status run_branch(gace_ctx* c, int k, hipStream_t s, bool use_graph) {
+    if (!use_graph) return launch_branch(c, k, s);
+    if (gace_status e = ensure_graph(c, k)) return e;
+    HIP_TRY(hipGraphLaunch(c->graph_exec[k], s), "graph launch");
+    return GACE_OK;
+}
+
+// init kernel, then the scan branch on st and the join branch on the side
+// stream concurrently (they touch disjoint state), joined back into st, each
+// branch between HIP timing events on its own stream and, with use_graph,
+// replayed from its captured graph.  The branches a batch has no items for
+// are left out: a single selectivity probe is init + scan on one stream.
+static gace_status launch_batch(gace_ctx* c, hipStream_t st, hipStream_t side, bool scans, bool joins, bool beside,
+                                bool use_graph) {
+    HIP_TRY(gace_launch_init(c->d_plan, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st), "init kernel");
+    if (joins) {
+        HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
+        HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
+        HIP_TRY(hipEventRecord(c->ev_j0, side), "join start event");
+        if (gace_status e = run_branch(c, beside ? 3 : 2, side, use_graph)) return e;
+        HIP_TRY(hipEventRecord(c->ev_j1, side), "join end event");
+    }
+    if (scans) {
+        HIP_TRY(hipEventRecord(c->ev_s0, st), "scan start event");
+        if (gace_status e = run_branch(c, beside ? 1 : 0, st, use_graph)) return e;
+        HIP_TRY(hipEventRecord(c->ev_s1, st), "scan end event");
+    }
+    if (joins) {
+        HIP_TRY(hipEventRecord(c->ev_join, side), "join event");
+        HIP_TRY(hipStreamWaitEvent(st, c->ev_join, 0), "join wait");
+    }
     return GACE_OK;
 }
 
@@ -262,16 +229,9 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     }
     HIP_TRY(hipEventRecord(c->ev0, st), "batch start event");
     const bool beside = scan_beside_joins(cb);
-    if (use_graph) {
-        const int k = (beside ? 4 : 0) | (cb.sel.empty() ? 0 : 2) | (cb.joins.empty() ? 0 : 1);
-        if (gace_status s = ensure_graph(c, k)) return s;
-        HIP_TRY(hipGraphLaunch(c->graph_exec[k], st), "graph launch");
-        c->last_timed = c->graph_timed[k];
-    } else {
-        if (gace_status s = launch_direct(c, st, c->side_stream, true, !cb.sel.empty(), !cb.joins.empty(), beside))
-            return s;
-        c->last_timed = true;
-    }
+    if (gace_status s = launch_batch(c, st, c->side_stream, !cb.sel.empty(), !cb.joins.empty(), beside, use_graph))
+        return s;
+    c->last_timed = true;
     HIP_TRY(hipEventRecord(c->ev1, st), "batch end event");
     // results to the pinned buffer: one small kernel writing host memory, or
     // (without a device address for it) one copy per region
@@ -546,7 +506,6 @@ gace_status gace_create(int hip_device, uint64_t workspace_bytes, gace_ctx** out
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->cap_side, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         gace_destroy(c);
         set_error("pinned staging / event / stream creation failed");
@@ -592,7 +551,6 @@ gace_status gace_destroy(gace_ctx* c) {
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
-    if (c->cap_side) (void)hipStreamDestroy(c->cap_side);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     for (hipEvent_t e : {c->ev_s0, c->ev_s1, c->ev_j0, c->ev_j1})
         if (e) (void)hipEventDestroy(e);

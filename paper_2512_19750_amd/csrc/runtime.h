@@ -104,12 +104,12 @@ struct gace_ctx {
     bool use_graph = true;                        // batched path: replay the captured graph
     hipStream_t side_stream = nullptr;   // join kernel runs here, concurrently with the scan kernel
     gace_schedule sched{};
-    // captured launch graphs for the current schedule, one per batch kind: (scan beside the joins << 2) | (has scans << 1) | has joins
+    // captured graphs of the batch branches for the current schedule: scan
+    // kernel (0, or 1 beside the joins), join stage (2, or 3 beside a scan)
     hipGraphExec_t graph_exec[8] = {};
     hipGraph_t graph[8] = {};
     gace_schedule graph_sched[8] = {};
-    bool graph_timed[8] = {};                     // the graph holds the per-kernel timing event nodes
-    hipStream_t cap_stream = nullptr, cap_side = nullptr;
+    hipStream_t cap_stream = nullptr;             // stream the branch graphs are captured on
     // stats of the last batch
     double last_kernel_ms = 0.0;
     uint64_t last_alg_bytes = 0, last_rows_preds = 0;

@@ -206,3 +206,30 @@ def test_open_loop_stream_equals_plain(env):
                           seed=5, duration_s=2.0, warm_s=0.2, ring=1024)
     assert r["mismatches"] == 0 and r["rejected_busy"] == 0
     assert r["counted"] > 0 and r["p99_ms"] >= r["p50_ms"] > 0
+
+
+def test_two_waiters_on_one_ticket(env):
+    """Two threads wait for the same ticket: one collects it, the other gets
+    GACE_EINVAL instead of blocking on a re-created entry."""
+    g, w, tabs, keys = env
+    kind, i = next(o for o in w.order if o[0] == "sel")
+    q = _req(g, w, tabs, keys, kind, i)
+    srv = g.gace_server_create(0, max_inflight=1, max_batch=4, queue_capacity=16, workspace_bytes=1 << 30)
+    out = []
+    try:
+        t = g.gace_server_submit(srv, q)
+
+        def waiter():
+            try:
+                out.append(("ok", g.gace_server_wait(srv, t, 30_000_000_000)))
+            except g.GaceError as e:
+                out.append(("err", e.status))
+        ths = [threading.Thread(target=waiter) for _ in range(2)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join(60)
+        assert not any(th.is_alive() for th in ths)
+    finally:
+        g.gace_server_destroy(srv)
+    assert sorted(out) == [("err", g.GACE_EINVAL), ("ok", 0)], out
