@@ -932,8 +932,8 @@ def main():
     ap.add_argument("--zone-rows", type=float, default=4e8)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the probe on a single MI355X "
-              "(multi-GPU sharding is a design note, not a code path); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the probe on a single MI355X "
+              "(sharding across GPUs is described, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.config in (1, 2):

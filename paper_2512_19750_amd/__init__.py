@@ -203,8 +203,7 @@ def lib():
         except Exception:
             pass
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libgace.so is not built: run __graft_entry__.build() (or "
-                               "python paper_2512_19750_amd/build.py) first")
+            raise RuntimeError("libgace.so is not built: run python paper_2512_19750_amd/build.py first")
         L = ctypes.CDLL(LIB_PATH)
         P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
         sig = {
