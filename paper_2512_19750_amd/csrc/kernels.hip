@@ -1031,22 +1031,43 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
     unsigned long long* s_w = (unsigned long long*)(lds + 320);     // kWaves wave totals
     uint32_t* s_b = (uint32_t*)(lds + kLdsMisc);                    // [P + 1] staged in LDS
     unsigned long long tot[2];
+    // loads of totals go out eight per thread at a time: one memory round
+    // trip per eight partitions of a thread instead of one per partition
+    constexpr uint32_t kBatch = 8;
+    auto stage = [&](const GACE_GLOBAL uint32_t* src) __attribute__((always_inline)) {
+        for (uint32_t i0 = threadIdx.x; i0 < P; i0 += kBatch * kWG) {
+            uint32_t v[kBatch];
+#pragma unroll
+            for (uint32_t u = 0; u < kBatch; ++u) v[u] = i0 + u * kWG < P ? src[i0 + u * kWG] : 0u;
+#pragma unroll
+            for (uint32_t u = 0; u < kBatch; ++u)
+                if (i0 + u * kWG < P) s_b[i0 + u * kWG] = v[u];
+        }
+    };
     // side 1 starts
-    for (uint32_t i = threadIdx.x; i < P; i += kWG) s_b[i] = b1[i];
+    stage(b1);
     __syncthreads();
     tot[1] = lds_prefix(s_b, P, s_w);
     for (uint32_t i = threadIdx.x; i <= P; i += kWG) b1[i] = s_b[i];
     // aggregation units (partitions interleaved over threads: coalesced reads;
     // the unit order only needs chunks, then whole partitions, then merges)
-    auto np_of = [&](uint32_t p) { return (uint64_t)b0[p] + (s_b[p + 1] - s_b[p]); };
+    auto np_of = [&](uint32_t p, uint32_t t0) { return (uint64_t)t0 + (s_b[p + 1] - s_b[p]); };
     unsigned long long n_chunk = 0, n_small = 0, n_split = 0;
-    for (uint32_t p = threadIdx.x; p < P; p += kWG) {
-        const uint64_t np = np_of(p);
-        if (np > kChunkKeys) {
-            n_chunk += (np + kChunkKeys - 1) / kChunkKeys;
-            n_split += 1;
-        } else if (np) {
-            n_small += 1;
+    for (uint32_t p0 = threadIdx.x; p0 < P; p0 += kBatch * kWG) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) v[u] = p0 + u * kWG < P ? b0[p0 + u * kWG] : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < kBatch; ++u) {
+            const uint32_t p = p0 + u * kWG;
+            if (p >= P) break;
+            const uint64_t np = np_of(p, v[u]);
+            if (np > kChunkKeys) {
+                n_chunk += (np + kChunkKeys - 1) / kChunkKeys;
+                n_split += 1;
+            } else if (np) {
+                n_small += 1;
+            }
         }
     }
     unsigned long long t_chunk, t_small, t_split;
@@ -1057,25 +1078,32 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
     GACE_GLOBAL uint32_t* done = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->done_off);
     const bool fits = t_chunk <= jd->max_chunks && t_chunk + t_small + t_split <= jd->max_units;
     if (fits) {
-        for (uint32_t p = threadIdx.x; p < P; p += kWG) {
-            const uint64_t np = np_of(p);
-            if (np > kChunkKeys) {
-                const uint32_t nc = (uint32_t)((np + kChunkKeys - 1) / kChunkKeys);
-                for (uint32_t c = 0; c < nc; ++c)
-                    put_unit(units + c_at + c, p, AU_CHUNK, c, (uint32_t)(c_at + c), (uint32_t)m_ord);
-                put_unit(units + t_chunk + t_small + m_ord, p, AU_MERGE, (uint32_t)c_at, nc, (uint32_t)m_ord);
-                done[m_ord] = 0;
-                c_at += nc;
-                m_ord += 1;
-            } else if (np) {
-                put_unit(units + s_at, p, AU_SMALL, 0, 0, 0);
-                ++s_at;
+        for (uint32_t p0 = threadIdx.x; p0 < P; p0 += kBatch * kWG) {
+            uint32_t v[kBatch];
+#pragma unroll
+            for (uint32_t u = 0; u < kBatch; ++u) v[u] = p0 + u * kWG < P ? b0[p0 + u * kWG] : 0u;
+            for (uint32_t u = 0; u < kBatch; ++u) {
+                const uint32_t p = p0 + u * kWG;
+                if (p >= P) break;
+                const uint64_t np = np_of(p, v[u]);
+                if (np > kChunkKeys) {
+                    const uint32_t nc = (uint32_t)((np + kChunkKeys - 1) / kChunkKeys);
+                    for (uint32_t c = 0; c < nc; ++c)
+                        put_unit(units + c_at + c, p, AU_CHUNK, c, (uint32_t)(c_at + c), (uint32_t)m_ord);
+                    put_unit(units + t_chunk + t_small + m_ord, p, AU_MERGE, (uint32_t)c_at, nc, (uint32_t)m_ord);
+                    done[m_ord] = 0;
+                    c_at += nc;
+                    m_ord += 1;
+                } else if (np) {
+                    put_unit(units + s_at, p, AU_SMALL, 0, 0, 0);
+                    ++s_at;
+                }
             }
         }
     }
     __syncthreads();
     // side 0 starts
-    for (uint32_t i = threadIdx.x; i < P; i += kWG) s_b[i] = b0[i];
+    stage(b0);
     __syncthreads();
     tot[0] = lds_prefix(s_b, P, s_w);
     for (uint32_t i = threadIdx.x; i <= P; i += kWG) b0[i] = s_b[i];
