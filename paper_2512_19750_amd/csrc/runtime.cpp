@@ -417,6 +417,10 @@ gace_status run_requests(gace_ctx* c, const gace_request* reqs, uint32_t n, gace
     if (e != hipSuccess) return hip_fail(e, "set device");
     if (gace_status z = apply_zonemaps(c, cb, reqs, st)) return z;
     gace_status s = run_compiled(c, cb, reqs, per_req, st, use_graph);
+    // the skipped-zone counters sit in pinned staging that a later call may
+    // reallocate: keep their sum now that the batch is done
+    c->last_zones_skipped = zones_skipped_last(c);
+    c->zm_n_last = 0;
     if (first == GACE_OK) first = s;
     return first;
 }
@@ -704,7 +708,7 @@ gace_status gace_last_kernel_stats(gace_ctx* ctx, gace_kernel_stats* out) {
     out->scan_alg_bytes = ctx->last_scan_bytes;
     out->join_alg_bytes = ctx->last_join_bytes;
     out->compile_ms = (float)ctx->last_compile_ms;
-    out->zones_skipped = zones_skipped_last(ctx);
+    out->zones_skipped = ctx->last_zones_skipped;
     return GACE_OK;
 }
 

@@ -98,6 +98,7 @@ struct gace_ctx {
     std::vector<const gace_zonemap*> zonemaps;
     const uint64_t* zm_counts = nullptr;
     uint32_t zm_n_last = 0;
+    uint64_t last_zones_skipped = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_done = nullptr, ev_fork = nullptr, ev_join = nullptr;
     // per-kernel timing of direct launches: scan kernel on the call's stream, join kernel on the side stream
     hipEvent_t ev_s0 = nullptr, ev_s1 = nullptr, ev_j0 = nullptr, ev_j1 = nullptr;
