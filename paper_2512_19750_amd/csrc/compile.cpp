@@ -673,7 +673,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
 
     // ---- joins: hash-partitioned key aggregation
     std::vector<JoinDesc> joins;
-    std::vector<Item> hist_items, off_items, base_items, scatter_items, scatter2_items, agg_items;
+    std::vector<Item> heavy_items, hist_items, off_items, base_items, scatter_items, scatter2_items, agg_items;
     uint64_t arena_static = 0;
     auto carve = [&](uint64_t bytes) {
         const uint64_t off = arena_static;
@@ -772,6 +772,8 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         J.units_off = carve((uint64_t)J.max_units * sizeof(AggUnit));
         J.chunk_off = carve((uint64_t)J.max_chunks * 4);
         J.done_off = carve(big * 4 + 64);
+        J.heavy_off = carve((uint64_t)kHeavySlots * 16);
+        heavy_items.push_back({IT_JHEAVY, j, 0, 0, 0, 0});
         for (const Item& it : my_items) {
             hist_items.push_back(it);
             Item sc = it;
@@ -873,7 +875,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     // partitioning kernel on the same stream)
     out.items.insert(out.items.end(), scan_items.begin(), scan_items.end());
     const uint32_t n_scan_items = (uint32_t)out.items.size();
-    for (auto* v : {&hist_items, &off_items, &base_items, &scatter_items, &scatter2_items})
+    for (auto* v : {&heavy_items, &hist_items, &off_items, &base_items, &scatter_items, &scatter2_items})
         out.items.insert(out.items.end(), v->begin(), v->end());
     const uint32_t n_join_end = (uint32_t)out.items.size();
     out.items.insert(out.items.end(), agg_items.begin(), agg_items.end());

@@ -6,10 +6,12 @@
 //            the scan (selectivity probe, Sec. III-B; Exp. D "Key-Only +
 //            Bitmask": only referenced columns are read, per-row predicate
 //            bits are reduced in registers and never stored)
-//   JHIST    per-item hash-partition counts of the sampled join keys
+//   JHEAVY   a join's heavy-hitter table, from a small sample of its keys
+//   JHIST    per-item hash-partition counts of the sampled join keys (heavy
+//            keys counted per table slot instead)
 //   JOFF     per-item offsets inside each partition
 //   JBASE    partition starts; the partition buffer is carved from the arena
-//   JSCATTER sampled keys -> their hash partitions
+//   JSCATTER sampled keys other than heavy ones -> their hash partitions
 //   JAGG     each partition aggregated in an LDS key table -> f_R(k), f_S(k)
 //            -> NDV (Eq. 1) and sum f_R f_S (key-only aggregation, Sec. III-B)
 // Items of a join wait on the previous phase's completion counter; the host
@@ -39,9 +41,16 @@ constexpr int kPerSmall = kTileKeys / 2 / kWG;
 constexpr uint32_t tile_lds_bytes(uint32_t keys) { return 3 * 132 * 4 + keys * 12; }   // cursors, counts, starts, tile
 constexpr uint32_t kBaseLdsBytes = ((1u << kPartBitsMax) + 1) * 4;                     // one side's partition starts
 constexpr uint32_t lds_max(uint32_t x, uint32_t y) { return x > y ? x : y; }
-constexpr uint32_t join_lds_bytes(uint32_t keys) {
-    return kLdsMisc + lds_max(tile_lds_bytes(keys), lds_max(kBaseLdsBytes, (1u << kPartBitsMax) * 4));
+// the heavy-hitter table (hashes, then the histogram items' per-slot counts)
+// sits above both a partitioning tile and a histogram row of the most
+// partitions; the sampling phase's counting table fits below it
+constexpr uint32_t heavy_lds_off(uint32_t keys) {
+    return (kLdsMisc + lds_max(tile_lds_bytes(keys), lds_max(kBaseLdsBytes, (1u << kPartBitsMax) * 4)) + 15) / 16 * 16;
 }
+constexpr uint32_t join_lds_bytes(uint32_t keys) { return heavy_lds_off(keys) + kHeavySlots * 12; }
+static_assert(kHeavyCount * 12 <= (1u << kPartBitsMax) * 4 && heavy_lds_off(kTileKeys / 2) % 16 == 0 &&
+                  heavy_lds_off(kTileKeys) % 16 == 0,
+              "heavy-hitter LDS layout");
 
 // explicit address spaces: pointers read from the plan are generic to the
 // compiler; global loads through them must not become flat loads, which would
@@ -812,6 +821,10 @@ __device__ __forceinline__ void scan_item(const BatchArgs& a, const PlanHdr& H, 
 // partition, hence NDV and sum f_R f_S.  A partition with more distinct keys
 // than one LDS table holds is split into residue classes of the hash and
 // aggregated in several passes, so the result is exact for any input.
+// Keys whose hash sits in the join's heavy-hitter table (JHEAVY) are counted
+// per slot by the histogram items, like the sentinel key, and skip the
+// partitioning and the LDS tables; the offset phase adds their share of the
+// results.  Under Zipf skew they are a large part of the keys.
 
 // MurmurHash3 64-bit finalizer (Appleby, public domain): a bijection on keys
 __device__ __forceinline__ uint64_t mix_key(uint64_t k) {
@@ -873,12 +886,96 @@ __device__ __forceinline__ void for_each_sampled_key(const JoinSide* D, uint64_t
     }
 }
 
+// Heavy hitters of one join, ahead of its histogram items.  Each side
+// contributes up to kHeavySample keys: all of them for a short side, else 8
+// runs of kWG consecutive rows spread evenly over the column (any rows would
+// do: the table only decides which keys skip the partitioning, never a
+// count).  A side's sample is counted in an LDS table (linear probing; a key
+// that finds no slot in 16 probes is left out); each hash seen at least
+// kHeavyMin times bids for its slot of the join's direct-mapped heavy table,
+// the higher count winning (ties: the later side, then the larger table
+// index).  The winners and zeroed per-slot counts go to the arena.
+template <int KP>
+__device__ void jheavy_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds) {
+    unsigned long long* s_key = (unsigned long long*)(lds + kLdsMisc);          // [kHeavyCount]
+    uint32_t* s_cnt = (uint32_t*)(s_key + kHeavyCount);                          // [kHeavyCount]
+    unsigned long long* s_win = (unsigned long long*)(lds + heavy_lds_off(KP * kWG));   // [kHeavySlots]
+    uint32_t* s_best = (uint32_t*)(s_win + kHeavySlots);                         // [kHeavySlots]
+    for (uint32_t i = threadIdx.x; i < kHeavySlots; i += kWG) {
+        s_win[i] = kEmptyHash;
+        s_best[i] = 0;
+    }
+    for (uint32_t sd = 0; sd < 2; ++sd) {
+        for (uint32_t i = threadIdx.x; i < kHeavyCount; i += kWG) {
+            s_key[i] = kEmptyHash;
+            s_cnt[i] = 0;
+        }
+        __syncthreads();
+        const JoinSide& D = jd->side[sd];
+        const uint64_t n = D.n;
+        const GACE_GLOBAL int64_t* keys = (const GACE_GLOBAL int64_t*)D.keys;
+        constexpr uint32_t kRuns = kHeavySample / kWG;
+        // one key at a time: unrolled, this phase's registers would raise
+        // the whole kernel's allocation past the partitioning tiles' needs
+#pragma unroll 1
+        for (uint32_t u = 0; u < kRuns; ++u) {
+            const uint64_t row = n <= kHeavySample ? (uint64_t)u * kWG + threadIdx.x
+                                                   : (n - kWG) * u / (kRuns - 1) + threadIdx.x;
+            const int64_t key = row < n ? keys[row] : (int64_t)kEmptyKey;
+            if ((uint64_t)key == kEmptyKey) continue;
+            const uint64_t h = mix_key((uint64_t)key);
+            uint32_t sl = (uint32_t)(h >> 21) & (kHeavyCount - 1);
+            for (int probe = 0; probe < 16; ++probe, sl = (sl + 1) & (kHeavyCount - 1)) {
+                unsigned long long cur = s_key[sl];
+                if (cur == kEmptyHash) cur = atomicCAS(&s_key[sl], (unsigned long long)kEmptyHash, h);
+                if (cur == kEmptyHash || cur == h) {
+                    atomicAdd(&s_cnt[sl], 1u);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        // bid: count above the side and the table index (unique per candidate)
+        for (uint32_t i = threadIdx.x; i < kHeavyCount; i += kWG) {
+            const uint32_t c = s_cnt[i];
+            if (c >= kHeavyMin) atomicMax(&s_best[(uint32_t)s_key[i] & (kHeavySlots - 1)], c << 12 | sd << 11 | i);
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kHeavyCount; i += kWG) {
+            const uint32_t c = s_cnt[i];
+            const uint32_t hs = (uint32_t)s_key[i] & (kHeavySlots - 1);
+            if (c >= kHeavyMin && s_best[hs] == (c << 12 | sd << 11 | i)) s_win[hs] = s_key[i];
+        }
+        __syncthreads();
+    }
+    GACE_GLOBAL unsigned long long* gh = (GACE_GLOBAL unsigned long long*)(a.arena_base + jd->heavy_off);
+    GACE_GLOBAL uint32_t* gc = (GACE_GLOBAL uint32_t*)(gh + kHeavySlots);
+    for (uint32_t i = threadIdx.x; i < kHeavySlots; i += kWG) {
+        gh[i] = s_win[i];
+        gc[i] = 0;
+        gc[kHeavySlots + i] = 0;
+    }
+}
+
+// the join's heavy-hitter hashes staged in LDS
+__device__ __forceinline__ void stage_heavy(const BatchArgs& a, const JoinDesc* jd, unsigned long long* s_hh) {
+    const GACE_GLOBAL u64x2* gh = (const GACE_GLOBAL u64x2*)(a.arena_base + jd->heavy_off);
+    for (uint32_t i = threadIdx.x; i < kHeavySlots / 2; i += kWG) ((u64x2*)s_hh)[i] = gh[i];
+}
+
+// Partition counts of an item's sampled keys; keys of the heavy table are
+// counted per slot instead (added to the join's per-slot counts at the end).
+template <int KP>
 __device__ void jhist_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds) {
     const JoinSide* D = &jd->side[it.side];
     JoinAcc& acc = a.accs[jd->acc];
     const uint32_t log2P = jd->log2P, P = 1u << log2P;
     unsigned long long* s_red = (unsigned long long*)(lds + 320);
     uint32_t* cnt = (uint32_t*)(lds + kLdsMisc);
+    unsigned long long* s_hh = (unsigned long long*)(lds + heavy_lds_off(KP * kWG));
+    uint32_t* s_hc = (uint32_t*)(s_hh + kHeavySlots);
+    stage_heavy(a, jd, s_hh);
+    for (uint32_t i = threadIdx.x; i < kHeavySlots; i += kWG) s_hc[i] = 0;
     for (uint32_t i = threadIdx.x; i < P; i += kWG) cnt[i] = 0;
     __syncthreads();
     unsigned long long nall = 0, nsent = 0;
@@ -888,11 +985,19 @@ __device__ void jhist_item(const BatchArgs& a, const JoinDesc* jd, const Item& i
             nsent += 1;
             return;
         }
-        atomicAdd(&cnt[part_of(mix_key(key), log2P)], 1u);
+        const uint64_t h = mix_key(key);
+        const uint32_t hs = (uint32_t)h & (kHeavySlots - 1);
+        if (s_hh[hs] == h) atomicAdd(&s_hc[hs], 1u);
+        else atomicAdd(&cnt[part_of(h, log2P)], 1u);
     });
     __syncthreads();
     GACE_GLOBAL uint32_t* row = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off) + (uint64_t)it.sub * P;
     for (uint32_t i = threadIdx.x; i < P; i += kWG) row[i] = cnt[i];
+    uint32_t* gc = (uint32_t*)(a.arena_base + jd->heavy_off + kHeavySlots * 8) + (uint64_t)it.side * kHeavySlots;
+    for (uint32_t i = threadIdx.x; i < kHeavySlots; i += kWG) {
+        const uint32_t c = s_hc[i];
+        if (c) atomicAdd(&gc[i], c);
+    }
     nall = block_sum(nall, s_red);
     nsent = block_sum(nsent, s_red);
     if (threadIdx.x == 0) {
@@ -1127,6 +1232,33 @@ __device__ void jbase_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds)
             acc.sent[1] = v[3];
         }
     }
+    // the heavy table's keys, counted outside the partitions: their share of
+    // the join size, the distinct counts and the keys seen once or twice
+    {
+        const GACE_GLOBAL uint32_t* gc = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->heavy_off + kHeavySlots * 8);
+        unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (uint32_t i = threadIdx.x; i < kHeavySlots; i += kWG) {
+            const uint32_t x = gc[i], y = gc[kHeavySlots + i];
+            v[0] += (unsigned long long)x * y;
+            v[1] += x != 0;
+            v[2] += y != 0;
+            v[3] += x == 1;
+            v[4] += y == 1;
+            v[5] += x == 2;
+            v[6] += y == 2;
+        }
+        unsigned long long* s_red = (unsigned long long*)(lds + 320);
+        for (int k = 0; k < 7; ++k) v[k] = block_sum(v[k], s_red);
+        if (threadIdx.x == 0) {
+            if (v[0]) atomicAdd(&acc.join, v[0]);
+            if (v[1]) atomicAdd(&acc.ndv[0], v[1]);
+            if (v[2]) atomicAdd(&acc.ndv[1], v[2]);
+            if (v[3]) atomicAdd(&acc.f1[0], v[3]);
+            if (v[4]) atomicAdd(&acc.f1[1], v[4]);
+            if (v[5]) atomicAdd(&acc.f2[0], v[5]);
+            if (v[6]) atomicAdd(&acc.f2[1], v[6]);
+        }
+    }
     if (threadIdx.x == 0) {
         acc.nkeys[0] = tot[0];
         acc.nkeys[1] = tot[1];
@@ -1166,8 +1298,9 @@ __device__ __forceinline__ TileLds tile_lds(uint8_t* lds) {
     return L;
 }
 
-// The tile's entries are keys (first pass: hashed here, sentinel keys
-// dropped) or hashes (second pass); the hashes are written out.  Digit of a
+// The tile's entries are keys (first pass: hashed here, sentinel keys and
+// keys of the heavy table hh dropped) or hashes (second pass); the hashes are
+// written out.  Digit of a
 // hash: (hash >> shift) mod F (F a power of two <= 128).  All digits are
 // computed first and the rank atomics issued back to back, so their LDS
 // latencies overlap; each entry's output index is recorded beside it, so the
@@ -1175,13 +1308,16 @@ __device__ __forceinline__ TileLds tile_lds(uint8_t* lds) {
 // L.cnt must be zero on entry (it is again on return).
 template <bool kKeys, int KP>
 __device__ void tile_partition(uint64_t (&k)[KP], uint32_t nt, uint32_t shift, uint32_t F,
-                               GACE_GLOBAL int64_t* dst, const TileLds& L) {
+                               GACE_GLOBAL int64_t* dst, const TileLds& L, const unsigned long long* hh) {
     uint32_t d[KP], r[KP];   // digit (~0: no entry at this position) and rank within it
 #pragma unroll
     for (int u = 0; u < KP; ++u) {
         const uint32_t pos = threadIdx.x + (uint32_t)u * kWG;
-        const bool ok = pos < nt && (!kKeys || k[u] != kEmptyKey);
-        if (kKeys) k[u] = mix_key(k[u]);
+        bool ok = pos < nt && (!kKeys || k[u] != kEmptyKey);
+        if (kKeys) {
+            k[u] = mix_key(k[u]);
+            ok = ok && hh[(uint32_t)k[u] & (kHeavySlots - 1)] != k[u];
+        }
         const uint32_t dg = F > 1 ? (uint32_t)(k[u] >> shift) & (F - 1) : 0u;
         d[u] = ok ? dg : ~0u;
     }
@@ -1315,6 +1451,8 @@ __device__ void jscatter_item(const BatchArgs& a, const JoinDesc* jd, const Item
         (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->base_off) + (uint64_t)it.side * (P + 1);
     const GACE_GLOBAL uint32_t* row = (const GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off) + (uint64_t)it.sub * P;
     const TileLds L = tile_lds<KP>(lds);
+    unsigned long long* s_hh = (unsigned long long*)(lds + heavy_lds_off(KP * kWG));
+    stage_heavy(a, jd, s_hh);
     for (uint32_t i = threadIdx.x; i < F1; i += kWG) {
         L.cur[i] = 0;
         L.cnt[i] = 0;
@@ -1329,7 +1467,7 @@ __device__ void jscatter_item(const BatchArgs& a, const JoinDesc* jd, const Item
                                (it.side ? acc.nkeys[0] : 0ull);
     const uint32_t shift = 64 - log2P1;
     for_each_tile<KP>(&jd->side[it.side], it.begin, it.end, lds,
-                      [&](uint64_t (&k)[KP], uint32_t nt) { tile_partition<true, KP>(k, nt, shift, F1, dst, L); });
+                      [&](uint64_t (&k)[KP], uint32_t nt) { tile_partition<true, KP>(k, nt, shift, F1, dst, L, s_hh); });
 }
 
 // second pass: a unit is one first-pass bucket of a group of consecutive
@@ -1404,7 +1542,7 @@ __device__ void jscatter2_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* 
             const uint32_t nt = (uint32_t)min((uint64_t)kTile, hi - t0);
             const bool more = t0 + kTile < hi;
             if (more) load(t0 + kTile, kn);
-            tile_partition<false, KP>(k, nt, shift, F2, dst, L);
+            tile_partition<false, KP>(k, nt, shift, F2, dst, L, nullptr);
             if (more) {
 #pragma unroll
                 for (int u2 = 0; u2 < KP; ++u2) k[u2] = kn[u2];
@@ -1897,8 +2035,15 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2, 8))
         const JoinDesc* jd = (const JoinDesc*)(a.plan + H.joins_off) + it.idx;
         JoinAcc& acc = a.accs[jd->acc];
         switch (it.kind) {
+            case IT_JHEAVY:
+                jheavy_item<KP>(a, jd, lds);
+                signal_count(&acc.heavy_done);
+                break;
             case IT_JHIST:
-                jhist_item(a, jd, it, lds);
+                if (wait_count(a, &acc.heavy_done, 1, acc, &s_flag)) {
+                    t1 = (uint64_t)wall_clock64();
+                    jhist_item<KP>(a, jd, it, lds);
+                }
                 signal_count(&acc.hist_done);
                 break;
             case IT_JOFF:

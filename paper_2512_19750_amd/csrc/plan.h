@@ -35,6 +35,14 @@ constexpr uint32_t kPass1BitsMax = 7;                  // first-pass fan-out at 
 static_assert(kPartBitsMax - kPartBitsMax / 2 <= kPass1BitsMax && kPartBitsMax / 2 <= 7,
               "partition passes wider than 128 ways");
 constexpr uint32_t kUnit2Keys = 1u << 17;              // target keys per second-pass unit
+// heavy hitters: keys whose hash holds a slot of a join's direct-mapped
+// table (slot = low hash bits) are counted per slot and never partitioned;
+// the table is filled from kHeavySample keys of each side, with the hashes
+// seen at least kHeavyMin times there
+constexpr uint32_t kHeavySlots = 1024;
+constexpr uint32_t kHeavySample = 2048;
+constexpr uint32_t kHeavyCount = 2048;                 // LDS counting-table slots for one side's sample
+constexpr uint32_t kHeavyMin = 2;
 
 // column program kinds
 enum : uint32_t { CP_LUT32 = 1, CP_RANK32 = 2, CP_RANK64 = 3 };
@@ -147,6 +155,7 @@ struct JoinDesc {
     uint64_t units_off;      // arena offset: aggregation units (AggUnit), capacity max_units
     uint64_t chunk_off;      // arena offset: per chunk slot, u32 entries emitted
     uint64_t done_off;       // arena offset: per split partition, u32 finished chunks
+    uint64_t heavy_off;      // arena offset: [kHeavySlots] u64 heavy hashes, then [2][kHeavySlots] u32 counts
     uint32_t max_units, max_chunks;
 };
 
@@ -178,7 +187,7 @@ struct JoinAcc {
     unsigned long long tmp_off;             // arena offset of the first-pass buffer (two-pass partitioning)
     uint32_t next_unit, n_units;
     uint32_t hist_done, off_done, base_done, scatter_done, agg_done, s2_done;
-    uint32_t next_s2, reserved;
+    uint32_t next_s2, heavy_done;
     unsigned long long f1[2], f2[2];        // distinct keys seen exactly once / twice per side
 };
 
@@ -189,7 +198,9 @@ struct Arena {                              // bump allocator for partition buff
 };
 
 // work item of the persistent batch kernel
-enum : uint32_t { IT_SCAN = 1, IT_JHIST = 2, IT_JOFF = 3, IT_JBASE = 4, IT_JSCATTER = 5, IT_JAGG = 6, IT_JSCATTER2 = 7 };
+enum : uint32_t {
+    IT_SCAN = 1, IT_JHIST = 2, IT_JOFF = 3, IT_JBASE = 4, IT_JSCATTER = 5, IT_JAGG = 6, IT_JSCATTER2 = 7, IT_JHEAVY = 8
+};
 struct Item {
     uint32_t kind;
     uint32_t idx;            // scan or join index

@@ -171,7 +171,7 @@ def test_tracing_records_every_item(env):
         tr, tpu = g.gace_get_trace(ctx)
         assert len(tr) > 0 and tpu > 0
         assert np.all(tr["t_end"] >= tr["t_ready"]) and np.all(tr["t_ready"] >= tr["t_begin"])
-        assert set(np.unique(tr["kind"]).tolist()) <= {1, 2, 3, 4, 5, 6, 7}
+        assert set(np.unique(tr["kind"]).tolist()) <= {1, 2, 3, 4, 5, 6, 7, 8}
         assert np.all(tr["xcc"] < 16)
     finally:
         g.gace_destroy(ctx)
