@@ -850,8 +850,9 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, un
     return t;
 }
 
-// calls f(key) for every sampled key of blocks [b0, b1) of one side; eight
-// loads per thread are issued before use
+// calls f(k, ok) for the sampled keys of blocks [b0, b1) of one side, eight
+// per thread at a time (k[u] is a key where ok[u]); the eight loads are
+// issued before use
 template <typename F>
 __device__ __forceinline__ void for_each_sampled_key(const JoinSide* D, uint64_t b0, uint64_t b1, uint8_t* lds,
                                                      F&& f) {
@@ -877,9 +878,10 @@ __device__ __forceinline__ void for_each_sampled_key(const JoinSide* D, uint64_t
                     const uint64_t rr = r + (uint64_t)u * kWG;
                     k[u] = (uint64_t)__builtin_nontemporal_load(keys + (rr < r1 ? rr : r1 - 1));
                 }
+                bool ok[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (r + (uint64_t)u * kWG < r1) f(k[u]);
+                for (int u = 0; u < 8; ++u) ok[u] = r + (uint64_t)u * kWG < r1;
+                f(k, ok);
             }
         }
         __syncthreads();
@@ -979,16 +981,24 @@ __device__ void jhist_item(const BatchArgs& a, const JoinDesc* jd, const Item& i
     for (uint32_t i = threadIdx.x; i < P; i += kWG) cnt[i] = 0;
     __syncthreads();
     unsigned long long nall = 0, nsent = 0;
-    for_each_sampled_key(D, it.begin, it.end, lds, [&](uint64_t key) {
-        nall += 1;
-        if (key == kEmptyKey) {
-            nsent += 1;
-            return;
+    // a key's count goes to its heavy slot or to its partition through one
+    // atomic on a per-lane address: two guarded atomics would make every
+    // wave issue both
+    for_each_sampled_key(D, it.begin, it.end, lds, [&](const uint64_t (&k)[8], const bool (&ok)[8]) {
+        uint64_t h[8], m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            h[u] = mix_key(k[u]);
+            m[u] = s_hh[(uint32_t)h[u] & (kHeavySlots - 1)];
         }
-        const uint64_t h = mix_key(key);
-        const uint32_t hs = (uint32_t)h & (kHeavySlots - 1);
-        if (s_hh[hs] == h) atomicAdd(&s_hc[hs], 1u);
-        else atomicAdd(&cnt[part_of(h, log2P)], 1u);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool sent = k[u] == kEmptyKey;
+            nall += ok[u];
+            nsent += ok[u] && sent;
+            uint32_t* c = m[u] == h[u] ? &s_hc[(uint32_t)h[u] & (kHeavySlots - 1)] : &cnt[part_of(h[u], log2P)];
+            if (ok[u] && !sent) atomicAdd(c, 1u);
+        }
     });
     __syncthreads();
     GACE_GLOBAL uint32_t* row = (GACE_GLOBAL uint32_t*)(a.arena_base + jd->rows_off) + (uint64_t)it.sub * P;
@@ -1316,7 +1326,8 @@ __device__ void tile_partition(uint64_t (&k)[KP], uint32_t nt, uint32_t shift, u
         bool ok = pos < nt && (!kKeys || k[u] != kEmptyKey);
         if (kKeys) {
             k[u] = mix_key(k[u]);
-            ok = ok && hh[(uint32_t)k[u] & (kHeavySlots - 1)] != k[u];
+            const bool heavy = hh[(uint32_t)k[u] & (kHeavySlots - 1)] == k[u];   // read for every position
+            ok = ok && !heavy;
         }
         const uint32_t dg = F > 1 ? (uint32_t)(k[u] >> shift) & (F - 1) : 0u;
         d[u] = ok ? dg : ~0u;

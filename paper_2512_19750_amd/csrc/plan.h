@@ -40,7 +40,7 @@ constexpr uint32_t kUnit2Keys = 1u << 17;              // target keys per second
 // the table is filled from kHeavySample keys of each side, with the hashes
 // seen at least kHeavyMin times there
 constexpr uint32_t kHeavySlots = 1024;
-constexpr uint32_t kHeavySample = 2048;
+constexpr uint32_t kHeavySample = 4096;
 constexpr uint32_t kHeavyCount = 2048;                 // LDS counting-table slots for one side's sample
 constexpr uint32_t kHeavyMin = 2;
 
