@@ -917,22 +917,32 @@ __device__ void jheavy_item(const BatchArgs& a, const JoinDesc* jd, uint8_t* lds
         const uint64_t n = D.n;
         const GACE_GLOBAL int64_t* keys = (const GACE_GLOBAL int64_t*)D.keys;
         constexpr uint32_t kRuns = kHeavySample / kWG;
-        // one key at a time: unrolled, this phase's registers would raise
-        // the whole kernel's allocation past the partitioning tiles' needs
+        // four keys at a time: fully unrolled, this phase's registers would
+        // raise the whole kernel's allocation past the partitioning tiles'
+        constexpr uint32_t kLoads = 4;
+        static_assert(kRuns % kLoads == 0, "sample runs in groups of four");
 #pragma unroll 1
-        for (uint32_t u = 0; u < kRuns; ++u) {
-            const uint64_t row = n <= kHeavySample ? (uint64_t)u * kWG + threadIdx.x
-                                                   : (n - kWG) * u / (kRuns - 1) + threadIdx.x;
-            const int64_t key = row < n ? keys[row] : (int64_t)kEmptyKey;
-            if ((uint64_t)key == kEmptyKey) continue;
-            const uint64_t h = mix_key((uint64_t)key);
-            uint32_t sl = (uint32_t)(h >> 21) & (kHeavyCount - 1);
-            for (int probe = 0; probe < 16; ++probe, sl = (sl + 1) & (kHeavyCount - 1)) {
-                unsigned long long cur = s_key[sl];
-                if (cur == kEmptyHash) cur = atomicCAS(&s_key[sl], (unsigned long long)kEmptyHash, h);
-                if (cur == kEmptyHash || cur == h) {
-                    atomicAdd(&s_cnt[sl], 1u);
-                    break;
+        for (uint32_t u0 = 0; u0 < kRuns; u0 += kLoads) {
+            int64_t key4[kLoads];
+#pragma unroll
+            for (uint32_t v = 0; v < kLoads; ++v) {
+                const uint32_t u = u0 + v;
+                const uint64_t row = n <= kHeavySample ? (uint64_t)u * kWG + threadIdx.x
+                                                       : (n - kWG) * u / (kRuns - 1) + threadIdx.x;
+                key4[v] = row < n ? keys[row] : (int64_t)kEmptyKey;
+            }
+#pragma unroll
+            for (uint32_t v = 0; v < kLoads; ++v) {
+                if ((uint64_t)key4[v] == kEmptyKey) continue;
+                const uint64_t h = mix_key((uint64_t)key4[v]);
+                uint32_t sl = (uint32_t)(h >> 21) & (kHeavyCount - 1);
+                for (int probe = 0; probe < 16; ++probe, sl = (sl + 1) & (kHeavyCount - 1)) {
+                    unsigned long long cur = s_key[sl];
+                    if (cur == kEmptyHash) cur = atomicCAS(&s_key[sl], (unsigned long long)kEmptyHash, h);
+                    if (cur == kEmptyHash || cur == h) {
+                        atomicAdd(&s_cnt[sl], 1u);
+                        break;
+                    }
                 }
             }
         }
