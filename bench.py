@@ -1141,6 +1141,9 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
+            # HBM bytes the counters saw per launch, over the same event time
+            "traffic_gbps": None if traffic is None else round(traffic / (dk["ms"] * 1e-3) / 1e9, 1),
+            "traffic_frac": None if traffic is None else round(traffic / (dk["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "kernel": dominant,
             "alg_bytes_per_launch": dk["alg_bytes"],
             "kernel_ms": round(dk["ms"], 4),
@@ -1149,7 +1152,10 @@ def main():
         },
         "kernels": {k: dict({"ms": round(v["ms"], 4), "alg_bytes": v["alg_bytes"],
                              "achieved_gbps": round(v["achieved_gbps"], 1),
-                             "traffic": stored_traffic(k)}, **({"kernels": v["kernels"]} if "kernels" in v else {}))
+                             "traffic": stored_traffic(k),
+                             "traffic_gbps": (None if stored_traffic(k) is None or not v["ms"] else
+                                              round(stored_traffic(k) / (v["ms"] * 1e-3) / 1e9, 1))},
+                            **({"kernels": v["kernels"]} if "kernels" in v else {}))
                     for k, v in per_kernel.items()},
         "read_ceiling": ceiling,
         "batch_kernel_span_ms": round(kernel_ms, 4),
