@@ -682,12 +682,12 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     };
     // Small join batches spread over the partitioning workers: items shrink
     // below item_rows keys only while the batch would have fewer items than
-    // half the workers, and second-pass units shrink to ~2 per worker.  A
-    // large batch keeps items of item_rows keys and units of kUnit2Keys; a
-    // lone join of 12.7 M keys gets 4x the items and units of a few thousand
-    // keys, so a Zipf-hot bucket no longer stalls its second pass.  (Smaller
-    // items for a join that already has more items than workers made its
-    // offset phases longer: 250 M keys, 8.1 -> 8.5 ms.)
+    // the workers, and second-pass units shrink to ~2 per worker.  A large
+    // batch keeps items of item_rows keys and units of kUnit2Keys; a lone
+    // join of 12.7 M keys gets one item per worker (512 instead of 49) and
+    // units of a few thousand keys, so a Zipf-hot bucket no longer stalls its
+    // second pass.  (Smaller items for a join that already has more items
+    // than workers made its offset phases longer: 250 M keys, 8.1 -> 8.5 ms.)
     double batch_keys = 0.0;
     for (uint32_t j = 0; j < join_reqs.size(); ++j) {
         const gace_request& r = reqs[join_reqs[j]];
@@ -697,7 +697,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         }
     }
     const double workers = std::max<uint32_t>(opt.workers, 1);
-    const double item_share = 2.0 * batch_keys / workers, unit_share = batch_keys / (2.0 * workers);
+    const double item_share = batch_keys / workers, unit_share = batch_keys / (2.0 * workers);
     for (uint32_t j = 0; j < join_reqs.size(); ++j) {
         const gace_request& r = reqs[join_reqs[j]];
         JoinDesc J;
@@ -725,9 +725,11 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         const uint32_t log2P2 = log2P > 6 ? log2P / 2 : 0;
         const uint32_t log2P1 = log2P - log2P2;
         // items large enough that the per-item partition counts (4 P bytes)
-        // stay small next to the item's keys (at most half of them)
+        // stay small next to the item's keys (at most a quarter of their 8 B
+        // each; a floor of 8 P keys left a lone 12.7 M-key join 192 items
+        // for 512 workers: 1.62 against 1.33 ms)
         const uint32_t item_keys =
-            std::max<uint32_t>((uint32_t)std::min<double>(opt.item_rows, item_share), 8u * P);
+            std::max<uint32_t>((uint32_t)std::min<double>(opt.item_rows, item_share), 2u * P);
         uint32_t item = 0;
         std::vector<Item> my_items;
         double keys_per_item = 1.0;
