@@ -850,10 +850,10 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, un
     return t;
 }
 
-// calls f(k, ok) for the sampled keys of blocks [b0, b1) of one side, eight
-// per thread at a time (k[u] is a key where ok[u]); the eight loads are
-// issued before use
-template <typename F>
+// calls f(k, ok) for the sampled keys of blocks [b0, b1) of one side, N
+// per thread at a time (k[u] is a key where ok[u]); the N loads are issued
+// before use
+template <int N, typename F>
 __device__ __forceinline__ void for_each_sampled_key(const JoinSide* D, uint64_t b0, uint64_t b1, uint8_t* lds,
                                                      F&& f) {
     uint32_t* s_w0 = (uint32_t*)lds;
@@ -869,18 +869,18 @@ __device__ __forceinline__ void for_each_sampled_key(const JoinSide* D, uint64_t
             keep &= keep - 1;
             const uint64_t r0 = (cb + (uint64_t)j) * B;
             const uint64_t r1 = (r0 + B < n) ? r0 + B : n;
-            for (uint64_t r = r0 + threadIdx.x; r < r1; r += 8 * kWG) {
-                uint64_t k[8];
+            for (uint64_t r = r0 + threadIdx.x; r < r1; r += (uint64_t)N * kWG) {
+                uint64_t k[N];
                 // unconditional loads (clamped in range): no branch makes the
                 // wave wait for one load before issuing the next
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < N; ++u) {
                     const uint64_t rr = r + (uint64_t)u * kWG;
                     k[u] = (uint64_t)__builtin_nontemporal_load(keys + (rr < r1 ? rr : r1 - 1));
                 }
-                bool ok[8];
+                bool ok[N];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) ok[u] = r + (uint64_t)u * kWG < r1;
+                for (int u = 0; u < N; ++u) ok[u] = r + (uint64_t)u * kWG < r1;
                 f(k, ok);
             }
         }
@@ -977,6 +977,11 @@ __device__ __forceinline__ void stage_heavy(const BatchArgs& a, const JoinDesc* 
 
 // Partition counts of an item's sampled keys; keys of the heavy table are
 // counted per slot instead (added to the join's per-slot counts at the end).
+// hist_keys(KP) loads per thread are in flight at once: the pass runs at the
+// partitioning kernel's occupancy, so its bytes in flight per CU come from
+// the loads per thread.  The 2048-key-tile variant keeps eight, which fit
+// its register budget beside a scan workgroup.
+constexpr int hist_keys(int kp) { return kp == kPerBig ? 16 : 8; }
 template <int KP>
 __device__ void jhist_item(const BatchArgs& a, const JoinDesc* jd, const Item& it, uint8_t* lds) {
     const JoinSide* D = &jd->side[it.side];
@@ -994,15 +999,16 @@ __device__ void jhist_item(const BatchArgs& a, const JoinDesc* jd, const Item& i
     // a key's count goes to its heavy slot or to its partition through one
     // atomic on a per-lane address: two guarded atomics would make every
     // wave issue both
-    for_each_sampled_key(D, it.begin, it.end, lds, [&](const uint64_t (&k)[8], const bool (&ok)[8]) {
-        uint64_t h[8], m[8];
+    constexpr int N = hist_keys(KP);
+    for_each_sampled_key<N>(D, it.begin, it.end, lds, [&](const uint64_t (&k)[N], const bool (&ok)[N]) {
+        uint64_t h[N], m[N];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < N; ++u) {
             h[u] = mix_key(k[u]);
             m[u] = s_hh[(uint32_t)h[u] & (kHeavySlots - 1)];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < N; ++u) {
             const bool sent = k[u] == kEmptyKey;
             nall += ok[u];
             nsent += ok[u] && sent;
