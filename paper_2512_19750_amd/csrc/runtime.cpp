@@ -82,7 +82,7 @@ static BatchArgsHost make_args(gace_ctx* c) {
 // A large batch whose scans run beside its joins for much of the join stage.
 // Then the scan gets one workgroup per CU and the join kernel its small-tile
 // variant: a CU holds the scan workgroup (168 VGPRs) and two join workgroups
-// (143 each), and more scan workgroups would only take CUs from the joins.
+// (160 each), and more scan workgroups would only take CUs from the joins.
 // Measured: a batch of 448 selectivity and 64 join requests over 50 GB
 // (scans reading an expected 14 B per sampled join key, 1.7e9 keys) gains up
 // to 6 % per step with graph replay; a served stream of batches of a few
