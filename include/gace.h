@@ -45,7 +45,8 @@
  *   GACE_EOVERFLOW reserved, never returned: each join side is limited to
  *                  2^32 - 1 keys (GACE_EINVAL beyond), so n_R * n_S, which
  *                  bounds sum f_R f_S, stays below 2^64
- *   GACE_EDEVICE   a HIP runtime error (the message carries HIP's text)
+ *   GACE_EDEVICE   a HIP runtime error (the message carries HIP's text), or a
+ *                  bounded wait inside a kernel that gave up
  *   GACE_EBUSY     the server queue is full
  *   GACE_ETIMEOUT  gace_server_wait timed out; the request is still running
  */
@@ -225,7 +226,8 @@ gace_status gace_join_freq(gace_ctx* ctx, const gace_keys* R, const gace_keys* S
    overlap on one GPU, from several threads or on several streams, race.
    Returns once the results are in counts / info (host memory).  Errors as
    gace_probe_selectivity, plus GACE_EDEVICE if the scratch's device address
-   cannot be found. */
+   cannot be found (counts untouched) or if a scan workgroup's bounded wait
+   gave up (counts unspecified). */
 gace_status gace_probe_selectivity_noalloc(const gace_table* table, const gace_predicates* preds,
                                            const gace_sample_spec* spec, uint64_t* counts, gace_probe_info* info,
                                            void* stream);

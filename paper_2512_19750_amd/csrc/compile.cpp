@@ -508,6 +508,7 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     out.scans.clear();
     out.jdesc.clear();
     out.n_counts = out.n_hist = 0;
+    out.err_off = 0;
     out.arena_static = 0;
     out.est_scan_bytes = out.est_join_keys = 0.0;
     out.status.assign(n, GACE_OK);
@@ -793,9 +794,10 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
         out.joins.push_back(jo);
     }
 
-    // one histogram entry counts the scan kernel's finished workgroups (per-request completion)
+    // one histogram entry counts the scan kernel's finished workgroups (per-request completion),
+    // the next its waits that gave up
     const uint32_t wg_done_off = n_hist;
-    n_hist += 1;
+    n_hist += 2;
 
     // ---- items
     // A kept block streams predicate group g only when its draw is below the
@@ -820,14 +822,19 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     // rows an item reads are its kept rows, or all its rows for the
     // row-by-row scan
     uint32_t item_rows = opt.item_rows;
+    bool small_batch = false;
     if (opt.workers) {
         double rows_read = 0.0;
         for (const ScanDesc& S : scans)
             rows_read += (double)S.n_rows *
                          (is_fine(S) || S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0);
         const double cap = std::max(1024.0, rows_read / (4.0 * opt.workers));
-        if (cap < item_rows) item_rows = (uint32_t)cap;
+        if (cap < item_rows) {
+            item_rows = (uint32_t)cap;
+            small_batch = true;
+        }
     }
+    bool any_spill = false;
     for (uint32_t s = 0; s < scans.size(); ++s) {
         ScanDesc& S = scans[s];
         const uint32_t* rc = rcum_flat.data() + S.req_begin;
@@ -851,6 +858,14 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
             bb = (want + per_tile - 1) / per_tile * per_tile;
         } else {
             bb = bpi_for(S.thr_max, S.log2B, rows);
+            // a sparse scan in a small batch: items of one 64-block sampling
+            // chunk, whose kept blocks beyond the first are spilled
+            const double p_keep = S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0;
+            if (small_batch && p_keep * 64.0 <= (double)kSpillChunkKept) {
+                S.spill = 1;
+                any_spill = true;
+                bb = 64;
+            }
         }
         if (bb == 0) continue;
         const double p = S.fine ? 1.0 : S.thr_max >= kThrAll ? 1.0 : (double)S.thr_max / 4294967296.0;
@@ -895,6 +910,10 @@ void compile_batch(const gace_request* reqs, uint32_t n, const CompileOptions& o
     H.n_scan_items = n_scan_items;
     H.n_join_end = n_join_end;
     H.wg_done_off = wg_done_off;
+    H.err_off = wg_done_off + 1;
+    out.err_off = H.err_off;
+    H.has_spill = any_spill ? 1u : 0u;
+    H.spill_cap = 0;   // set at launch, from the room left in the item region
     H.arena_static = arena_static;
     std::vector<uint8_t>& blob = out.plan;
     {

@@ -49,6 +49,7 @@ struct CompiledBatch {
     std::vector<gace_status> status; // per caller request (validation result)
     std::vector<std::string> errors;
     uint32_t n_counts = 0, n_hist = 0;
+    uint32_t err_off = 0;            // hist entry counting the scan kernel's waits that gave up
     uint64_t arena_static = 0;       // joins' per-item tables at the start of the arena
     double est_scan_bytes = 0.0;     // expected bytes the scans read (sum of the items' costs)
     double est_join_keys = 0.0;      // expected sampled keys of the joins

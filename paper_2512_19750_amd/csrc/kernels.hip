@@ -26,6 +26,7 @@
 namespace gace {
 
 constexpr int kWG = 256;
+constexpr int kHeads = 6;                        // queue heads and counters (BatchArgs::head)
 constexpr int kWaves = kWG / 64;
 constexpr uint32_t kScanLdsGroups = 32;          // per-item LDS counters for the first 32 groups
 constexpr uint32_t kScanLdsHist = 128;           // per-item LDS sample histogram for scans of < 128 requests
@@ -65,7 +66,8 @@ static_assert(kHeavyCount * 12 <= (1u << kPartBitsMax) * 4 && heavy_lds_off(kTil
 struct BatchArgs {
     const uint8_t* plan;
     const Item* items;
-    uint32_t* head;            // [0] scan queue, [1] join partitioning queue, [2] aggregation queue
+    uint32_t* head;            // [0] scan queue, [1] join partitioning queue, [2] aggregation queue,
+                               // [3] spill entries claimed, [4] spill entries taken, [5] scan items done
     unsigned long long* counts;
     unsigned long long* hist;
     JoinAcc* accs;
@@ -692,6 +694,80 @@ __device__ __forceinline__ void scan_fine(const BatchArgs& a, const ScanDesc& S,
     }
 }
 
+// Group-major pass over the blocks in scan_keep (bit j = block cb + j) of
+// one chunk: group g streams every block whose requests reach into it, each
+// with its own active bits (s_act[j]).  Counts of the first n_lds_groups
+// groups go to the LDS counters, the rest straight to the global ones.
+__device__ __forceinline__ void scan_groups(const BatchArgs& a, const ScanDesc& S,
+                                            const GACE_CONST GroupDesc* groups, const GACE_CONST ColProg* cols,
+                                            const uint32_t* slots, uint32_t n_lds_groups, unsigned long long scan_keep,
+                                            uint64_t cb, const uint32_t* s_act, uint32_t* s_cnt, uint8_t* s_tab,
+                                            int* s_staged, int lane, int wave) {
+    const uint64_t B = 1ull << S.log2B;
+    for (uint32_t g = 0;; ++g) {
+        const unsigned long long blocks_g = __ballot(((scan_keep >> lane) & 1ull) && s_act[lane] > g * 64);
+        if (!blocks_g) break;
+        const GroupDesc G = cgroup(groups + g);
+        uint32_t cnt;
+        if (G.tab_bytes <= kGroupTabBudget) {
+            if (*s_staged != (int)g) {
+                __syncthreads();
+                const uint4* src = (const uint4*)(a.plan + G.tab_off);
+                uint4* dst = (uint4*)s_tab;
+                for (uint32_t i = threadIdx.x; i < G.tab_bytes / 16; i += kWG) dst[i] = src[i];
+                __syncthreads();
+                if (threadIdx.x == 0) *s_staged = (int)g;
+            }
+            cnt = scan_blocks<3>(cols, G.col_begin, G.col_end, s_tab, blocks_g, cb, B, S.n_rows, G.base_mask, s_act,
+                                 g, lane, wave, a.count_mode);
+        } else {
+            cnt = scan_blocks<1>(cols, G.col_begin, G.col_end, a.plan + G.tab_off, blocks_g, cb, B, S.n_rows,
+                                 G.base_mask, s_act, g, lane, wave, a.count_mode);
+        }
+        if (cnt) {
+            if (g < n_lds_groups) atomicAdd(&s_cnt[g * 64 + lane], cnt);
+            else atomicAdd(&a.counts[slots[G.slot_index + lane]], (unsigned long long)cnt);
+        }
+        if (S.n_groups > 1) __syncthreads();   // the staged table may be replaced by the next group
+    }
+}
+
+// the spill list: the item region after the items kept there
+__device__ __forceinline__ Item* spill_list(const BatchArgs& a, const PlanHdr& H) {
+    return const_cast<Item*>(a.items) + (H.items_off ? 0u : H.n_items);
+}
+
+// Wave 0 appends every kept block of the chunk after the first to the spill
+// list (an entry per block: scan, block, its predicate bits; its ready word
+// stored last, with release); blocks that find the list full stay.  Returns
+// the blocks this item still scans.
+__device__ __forceinline__ unsigned long long spill_blocks(const BatchArgs& a, const PlanHdr& H, uint32_t scan,
+                                                           uint64_t cb, unsigned long long scan_keep,
+                                                           const uint32_t* s_act, unsigned long long* s_keep2) {
+    if (threadIdx.x < 64) {
+        const uint32_t lane = threadIdx.x;
+        const unsigned long long first = scan_keep & (~scan_keep + 1ull);
+        bool moved = false;
+        if (((scan_keep >> lane) & 1ull) && !((first >> lane) & 1ull)) {
+            const uint32_t slot = atomicAdd(&a.head[3], 1u);
+            if (slot < H.spill_cap) {
+                Item* e = spill_list(a, H) + slot;
+                e->kind = IT_SCAN;
+                e->idx = scan;
+                e->side = s_act[lane];
+                e->begin = cb + lane;
+                e->end = cb + lane + 1;
+                __hip_atomic_store(&e->sub, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                moved = true;
+            }
+        }
+        const unsigned long long out = __ballot(moved);
+        if (lane == 0) *s_keep2 = scan_keep & ~out;
+    }
+    __syncthreads();
+    return *s_keep2;
+}
+
 // ------------------------------------------------------------------ scan item
 __device__ __forceinline__ void scan_item(const BatchArgs& a, const PlanHdr& H, const Item& it, uint8_t* lds) {
     const ScanDesc S = ((const ScanDesc*)(a.plan + H.scans_off))[it.idx];
@@ -704,6 +780,7 @@ __device__ __forceinline__ void scan_item(const BatchArgs& a, const PlanHdr& H, 
     uint32_t* s_w0 = (uint32_t*)lds;
     unsigned long long* s_keep = (unsigned long long*)(lds + 256);
     int* s_staged = (int*)(lds + 264);
+    unsigned long long* s_keep2 = (unsigned long long*)(lds + 272);
     uint32_t* s_k = (uint32_t*)(lds + 384);
     uint32_t* s_act = s_w0;   // per block: predicate bits its requests own (replaces w0 once k is known)
     uint32_t* s_cnt = (uint32_t*)(lds + kLdsMisc);
@@ -769,36 +846,10 @@ __device__ __forceinline__ void scan_item(const BatchArgs& a, const PlanHdr& H, 
             }
             scan_keep = keep & ~__ballot(skip);
         }
-        // group-major: group g streams every kept block whose requests reach
-        // into it, each block with its own active bits
-        {
-            for (uint32_t g = 0;; ++g) {
-                const unsigned long long blocks_g = __ballot(((scan_keep >> lane) & 1ull) && s_act[lane] > g * 64);
-                if (!blocks_g) break;
-                const GroupDesc G = cgroup(groups + g);
-                uint32_t cnt;
-                if (G.tab_bytes <= kGroupTabBudget) {
-                    if (*s_staged != (int)g) {
-                        __syncthreads();
-                        const uint4* src = (const uint4*)(a.plan + G.tab_off);
-                        uint4* dst = (uint4*)s_tab;
-                        for (uint32_t i = threadIdx.x; i < G.tab_bytes / 16; i += kWG) dst[i] = src[i];
-                        __syncthreads();
-                        if (threadIdx.x == 0) *s_staged = (int)g;
-                    }
-                    cnt = scan_blocks<3>(cols, G.col_begin, G.col_end, s_tab, blocks_g, cb, B, S.n_rows,
-                                         G.base_mask, s_act, g, lane, wave, a.count_mode);
-                } else {
-                    cnt = scan_blocks<1>(cols, G.col_begin, G.col_end, a.plan + G.tab_off, blocks_g, cb, B,
-                                         S.n_rows, G.base_mask, s_act, g, lane, wave, a.count_mode);
-                }
-                if (cnt) {
-                    if (g < n_lds_groups) atomicAdd(&s_cnt[g * 64 + lane], cnt);
-                    else atomicAdd(&a.counts[slots[G.slot_index + lane]], (unsigned long long)cnt);
-                }
-                if (S.n_groups > 1) __syncthreads();   // the staged table may be replaced by the next group
-            }
-        }
+        // a sparse scan keeps the chunk's first kept block and spills the rest
+        if (S.spill && H.spill_cap) scan_keep = spill_blocks(a, H, it.idx, cb, scan_keep, s_act, s_keep2);
+        scan_groups(a, S, groups, cols, slots, n_lds_groups, scan_keep, cb, s_act, s_cnt, s_tab, s_staged, lane,
+                    wave);
         __syncthreads();
     }
     __syncthreads();
@@ -811,6 +862,34 @@ __device__ __forceinline__ void scan_item(const BatchArgs& a, const PlanHdr& H, 
             const unsigned long long v = s_hist[i];
             if (v) atomicAdd(&a.hist[S.hist_off + i], v);
         }
+}
+
+// One spilled block: the group-major pass over it alone (its sample
+// histogram entry was counted by the item that decided it).
+__device__ __forceinline__ void scan_spill_task(const BatchArgs& a, const PlanHdr& H, uint32_t scan, uint64_t block,
+                                                uint32_t act, uint8_t* lds) {
+    const ScanDesc S = ((const ScanDesc*)(a.plan + H.scans_off))[scan];
+    const GACE_CONST GroupDesc* groups = (const GACE_CONST GroupDesc*)(a.plan + H.groups_off) + S.group_begin;
+    const GACE_CONST ColProg* cols = (const GACE_CONST ColProg*)(a.plan + H.cols_off);
+    const uint32_t* slots = (const uint32_t*)(a.plan + H.slots_off);
+    uint32_t* s_act = (uint32_t*)lds;
+    int* s_staged = (int*)(lds + 264);
+    uint32_t* s_cnt = (uint32_t*)(lds + kLdsMisc);
+    uint8_t* s_tab = lds + kLdsMisc + kLdsCnt + kLdsHist + kLdsThr;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t n_lds_groups = S.n_groups < kScanLdsGroups ? S.n_groups : kScanLdsGroups;
+    for (uint32_t i = threadIdx.x; i < n_lds_groups * 64; i += kWG) s_cnt[i] = 0;
+    if (threadIdx.x == 0) {
+        *s_staged = -1;
+        s_act[0] = act;
+    }
+    __syncthreads();
+    scan_groups(a, S, groups, cols, slots, n_lds_groups, 1ull, block, s_act, s_cnt, s_tab, s_staged, lane, wave);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_lds_groups * 64; i += kWG) {
+        const uint32_t c = s_cnt[i];
+        if (c) atomicAdd(&a.counts[slots[groups[i >> 6].slot_index + (i & 63)]], (unsigned long long)c);
+    }
 }
 
 // ------------------------------------------------------------------ joins
@@ -2015,6 +2094,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 8))
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     __shared__ uint32_t s_item;
     const PlanHdr H = *(const PlanHdr*)a.plan;
+    const bool spill = H.has_spill && H.spill_cap;
     bool worked = false;
     for (;;) {
         const uint32_t idx = pop_item(&a.head[0], 0, &s_item);
@@ -2025,6 +2105,55 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 8))
         worked = true;
         __syncthreads();
         trace_item(a, H, idx, it, t0, t0);
+        if (spill && threadIdx.x == 0) {
+            // this item's spill claims and entries come before its count
+            __threadfence();
+            atomicAdd(&a.head[5], 1u);
+        }
+    }
+    if (spill) {
+        // Run spilled blocks: a ticket names an entry; it is run once it is
+        // written, and the workgroup leaves when every item is done and the
+        // ticket lies past the entries claimed.  The items never wait, so
+        // the wait ends; it gives up, failing the scans, after kSpillPolls.
+        __shared__ uint32_t s_ok;
+        __shared__ uint32_t s_task[2];
+        __shared__ unsigned long long s_block;
+        Item* list = spill_list(a, H);
+        for (;;) {
+            if (threadIdx.x == 0) {
+                const uint32_t t = atomicAdd(&a.head[4], 1u);
+                uint32_t ok = 0;   // 1: run entry t, 0: no entry left, 2: gave up
+                for (uint64_t polls = 0;; ++polls) {
+                    if (t < H.spill_cap &&
+                        __hip_atomic_load(&list[t].sub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 1u) {
+                        ok = 1;
+                        break;
+                    }
+                    if (__hip_atomic_load(&a.head[5], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= H.n_scan_items) {
+                        const uint32_t claimed = __hip_atomic_load(&a.head[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (t >= (claimed < H.spill_cap ? claimed : H.spill_cap)) break;
+                    }
+                    if (polls >= kSpillPolls) {
+                        ok = 2;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                if (ok == 1) {
+                    s_task[0] = list[t].idx;
+                    s_task[1] = list[t].side;
+                    s_block = list[t].begin;
+                }
+                if (ok == 2) atomicAdd(&a.hist[H.err_off], 1ull);
+                s_ok = ok;
+            }
+            __syncthreads();
+            if (s_ok != 1) break;
+            scan_spill_task(a, H, s_task[0], s_block, s_task[1], lds);
+            worked = true;
+            __syncthreads();
+        }
     }
     if (H.early && H.n_scan_items) {
         // the last workgroup to finish publishes every counter and histogram;
@@ -2130,7 +2259,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))
 
 // zero the per-batch accumulators (a kernel, not a memset, so it can be
 // captured in a graph and replayed)
-__global__ void __launch_bounds__(kWG) gace_init_kernel(const uint8_t* plan, uint32_t* head,
+__global__ void __launch_bounds__(kWG) gace_init_kernel(const uint8_t* plan, Item* items, uint32_t* head,
                                                         unsigned long long* counts, unsigned long long* hist,
                                                         JoinAcc* accs, Arena* arena) {
     const PlanHdr H = *(const PlanHdr*)plan;
@@ -2140,10 +2269,11 @@ __global__ void __launch_bounds__(kWG) gace_init_kernel(const uint8_t* plan, uin
     for (uint64_t i = tid; i < H.n_hist; i += stride) hist[i] = 0;
     const uint64_t nacc = (uint64_t)H.n_joins * (sizeof(JoinAcc) / 8);
     for (uint64_t i = tid; i < nacc; i += stride) ((unsigned long long*)accs)[i] = 0;
+    // spill-list entries start unwritten (their ready words cleared)
+    Item* spill = items + (H.items_off ? 0u : H.n_items);
+    for (uint64_t i = tid; i < H.spill_cap; i += stride) spill[i].sub = 0;
     if (tid == 0) {
-        head[0] = 0;
-        head[1] = 0;
-        head[2] = 0;
+        for (int q = 0; q < kHeads; ++q) head[q] = 0;
         arena->used = H.arena_static;
     }
 }
@@ -2415,11 +2545,11 @@ const void* gace_kernel_handle(int which) {
 }
 
 // launchers used by the host runtime (internal; not part of the public ABI)
-hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,
-                            hipStream_t stream) {
+hipError_t gace_launch_init(const void* plan, void* items, void* head, void* counts, void* hist, void* accs,
+                            void* arena, hipStream_t stream) {
     (void)hipGetLastError();   // report this launch's error, not an earlier call's
     hipLaunchKernelGGL(gace::gace_init_kernel, dim3(256), dim3(gace::kWG), 0, stream, (const uint8_t*)plan,
-                       (uint32_t*)head, (unsigned long long*)counts, (unsigned long long*)hist,
+                       (gace::Item*)items, (uint32_t*)head, (unsigned long long*)counts, (unsigned long long*)hist,
                        (gace::JoinAcc*)accs, (gace::Arena*)arena);
     return hipGetLastError();
 }

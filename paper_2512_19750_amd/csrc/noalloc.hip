@@ -8,6 +8,7 @@
 // path's own (init + scan); only the buffers differ.  Every process keeps
 // one copy of the array per GPU it runs on until it ends; all calls on one
 // GPU share that copy, so calls that overlap on one GPU race.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -132,6 +133,11 @@ extern "C" gace_status gace_probe_selectivity_noalloc(const gace_table* table, c
     if (cb.n_hist > kNaMaxHist || cb.n_hist * 8ull > kNaHistCap)
         return too_big("the sample histogram", cb.n_hist * 8ull, kNaMaxHist * 8ull);
     ((PlanHdr*)cb.plan.data())->trace = 0;
+    // sparse scans' spill list: the item region after the items
+    ((PlanHdr*)cb.plan.data())->spill_cap =
+        ((PlanHdr*)cb.plan.data())->has_spill
+            ? (uint32_t)std::min<uint64_t>(kSpillMax, (kNaItemsCap - items_b) / sizeof(Item))
+            : 0u;
 
     uint8_t* plan = d.ptr;
     uint8_t* items = plan + kNaPlanCap;
@@ -145,7 +151,7 @@ extern "C" gace_status gace_probe_selectivity_noalloc(const gace_table* table, c
     NA_TRY(hipMemcpyAsync(plan, cb.plan.data(), plan_b, hipMemcpyHostToDevice, st), "plan upload");
     if (items_b) NA_TRY(hipMemcpyAsync(items, cb.items.data(), items_b, hipMemcpyHostToDevice, st), "item upload");
     // the init kernel zeroes the counters, the histogram and the queue heads
-    NA_TRY(gace_launch_init(plan, head, cnt, hist, misc + 512, arena, st), "init kernel");
+    NA_TRY(gace_launch_init(plan, items, head, cnt, hist, misc + 512, arena, st), "init kernel");
     BatchArgsHost a;
     std::memset(&a, 0, sizeof(a));
     a.plan = plan;
@@ -157,7 +163,10 @@ extern "C" gace_status gace_probe_selectivity_noalloc(const gace_table* table, c
     a.arena = arena;
     a.count_mode = sc.count_mode;
     a.spin_limit = 1ull << 24;
-    NA_TRY(gace_launch_scan(&a, (uint32_t)d.n_cu * sc.wgs_per_cu, st), "scan kernel");
+    // spilling scans run one workgroup per CU (as in the context path)
+    const PlanHdr* hp = (const PlanHdr*)cb.plan.data();
+    const uint32_t per_cu = hp->has_spill && hp->spill_cap ? 1u : sc.wgs_per_cu;
+    NA_TRY(gace_launch_scan(&a, (uint32_t)d.n_cu * per_cu, st), "scan kernel");
 
     const SelOut& so = cb.sel[0];
     const ScanDesc& S = cb.scans[so.scan];
@@ -167,6 +176,10 @@ extern "C" gace_status gace_probe_selectivity_noalloc(const gace_table* table, c
                "counts download");
     if (cb.n_hist) NA_TRY(hipMemcpyAsync(h, hist, 8ull * cb.n_hist, hipMemcpyDeviceToHost, st), "hist download");
     NA_TRY(hipStreamSynchronize(st), "synchronize");
+    if (h[cb.err_off]) {
+        set_error("a scan workgroup's wait for spilled blocks gave up before the probe's items finished");
+        return GACE_EDEVICE;
+    }
     if (info) {
         uint64_t rows = 0, blocks = 0;
         for (uint32_t k = so.rank + 1; k <= S.n_req; ++k) {

@@ -61,7 +61,22 @@ struct PlanHdr {
     uint32_t seq;            // ... raising their host flags to this batch number
     uint32_t wg_done_off;    // hist entry counting the scan kernel's finished workgroups
     uint32_t items_off;      // byte offset of the work items in the plan buffer (0: in their own region)
+    uint32_t has_spill;      // some scan passes kept blocks beyond an item's first to the spill list
+    uint32_t spill_cap;      // spill-list entries available after the items (0: no list, blocks stay local)
+    uint32_t err_off;        // hist entry counting scan-kernel waits that gave up (nonzero fails the scans)
+    uint32_t reserved;
 };
+
+// Sparse scans in a small batch: an item scans the first kept block of its
+// 64-block chunk and appends the chunk's other kept blocks to a spill list in
+// the item region, after the items (an Item each: kind, scan index, the
+// block's predicate bits in `side`, block range; `sub` becomes 1 once the
+// entry is written).  Workgroups that find the item queue empty run the
+// list, so a probe's kept tiles spread one per workgroup instead of queueing
+// behind each other inside one item.
+constexpr uint32_t kSpillMax = 16384;                  // spill-list entries per batch, at most
+constexpr uint32_t kSpillChunkKept = 8;                // spill when at most this many kept blocks per 64 expected
+constexpr uint64_t kSpillPolls = 1ull << 26;           // a drain wait gives up after this many polls
 
 // Per-request completion.  When a plan asks for it, the last workgroup of
 // the scan kernel to finish copies all counters and sample histograms, and
@@ -98,7 +113,7 @@ struct ScanDesc {
                                   // scan can hold on zone z, kZoneRows rows); 0: no zone map
     uint64_t n_zones;
     uint32_t fine;                // blocks under 4096 rows decided row by row in whole tiles (items tile-aligned)
-    uint32_t reserved;
+    uint32_t spill;               // items are 64-block chunks whose kept blocks beyond the first are spilled
 };
 
 constexpr uint32_t kZoneLog2 = 12;                     // zone-map zones of 4096 rows

@@ -165,8 +165,9 @@ static gace_status run_branch(gace_ctx* c, int k, hipStream_t s, bool use_graph)
 // replayed from its captured graph.  The branches a batch has no items for
 // are left out: a single selectivity probe is init + scan on one stream.
 static gace_status launch_batch(gace_ctx* c, hipStream_t st, hipStream_t side, bool scans, bool joins, bool beside,
-                                bool use_graph) {
-    HIP_TRY(gace_launch_init(c->d_plan, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st), "init kernel");
+                                bool scan_one_per_cu, bool use_graph) {
+    HIP_TRY(gace_launch_init(c->d_plan, c->d_items, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st),
+            "init kernel");
     if (joins) {
         HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
         HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0), "fork wait");
@@ -176,7 +177,7 @@ static gace_status launch_batch(gace_ctx* c, hipStream_t st, hipStream_t side, b
     }
     if (scans) {
         HIP_TRY(hipEventRecord(c->ev_s0, st), "scan start event");
-        if (gace_status e = run_branch(c, beside ? 1 : 0, st, use_graph)) return e;
+        if (gace_status e = run_branch(c, beside || scan_one_per_cu ? 1 : 0, st, use_graph)) return e;
         HIP_TRY(hipEventRecord(c->ev_s1, st), "scan end event");
     }
     if (joins) {
@@ -216,7 +217,12 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     hs->seq = c->seq;
     // the items follow the plan in one upload when both fit the plan region
     const uint64_t items_at = (plan_b + 15) / 16 * 16;
-    if (items_at + items_b <= kPlanCap) {
+    const bool items_in_plan = items_at + items_b <= kPlanCap;
+    // sparse scans' spill list: the item region after the items kept there
+    hs->spill_cap = hs->has_spill ? (uint32_t)std::min<uint64_t>(
+                                        kSpillMax, (kItemsCap - (items_in_plan ? 0 : items_b)) / sizeof(Item))
+                                  : 0u;
+    if (items_in_plan) {
         hs->items_off = items_b ? (uint32_t)items_at : 0u;
         std::memcpy(c->h_stage + items_at, cb.items.data(), items_b);
         HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, items_b ? items_at + items_b : plan_b, hipMemcpyHostToDevice,
@@ -229,7 +235,12 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     }
     HIP_TRY(hipEventRecord(c->ev0, st), "batch start event");
     const bool beside = scan_beside_joins(cb);
-    if (gace_status s = launch_batch(c, st, c->side_stream, !cb.sel.empty(), !cb.joins.empty(), beside, use_graph))
+    // a batch with spilling scans runs one scan workgroup per CU: its kept
+    // tiles, each bound by its own CU's issue and LDS latency, then land on
+    // different CUs instead of sharing them
+    const bool one_per_cu = hs->has_spill && hs->spill_cap;
+    if (gace_status s = launch_batch(c, st, c->side_stream, !cb.sel.empty(), !cb.joins.empty(), beside, one_per_cu,
+                                     use_graph))
         return s;
     c->last_timed = true;
     HIP_TRY(hipEventRecord(c->ev1, st), "batch end event");
@@ -316,7 +327,8 @@ void collect_published(gace_ctx* c, CompiledBatch& cb, const gace_request* reqs,
                        std::vector<std::pair<uint32_t, gace_status>>& out) {
     if (!c->last_early) return;
     auto flag = [&](uint32_t f) { return __atomic_load_n(&c->h_flags[f], __ATOMIC_ACQUIRE) == c->seq; };
-    if (!cb.sel.empty() && !done[cb.sel[0].req] && flag(0))
+    const unsigned long long* hist = (const unsigned long long*)(c->h_result + kCountsCap);
+    if (!cb.sel.empty() && !done[cb.sel[0].req] && flag(0) && hist[cb.err_off] == 0)
         for (const SelOut& so : cb.sel) {
             write_sel(c, cb, so, reqs);
             done[so.req] = 1;
@@ -349,9 +361,15 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
         for (uint32_t k = 1; k <= S.n_req; ++k) kept_rows += hist[S.hist_off + 2 * k];
         alg += kept_rows * S.row_bytes;
     }
+    const bool scan_failed = !cb.sel.empty() && hist[cb.err_off] != 0;
     for (const SelOut& so : cb.sel) {
         const ScanDesc& S = cb.scans[so.scan];
         uint64_t rows = 0;
+        if (scan_failed) {
+            set_error("a scan workgroup's wait for spilled blocks gave up before the batch's items finished");
+            if (per_req) per_req[so.req] = GACE_EDEVICE;
+            continue;
+        }
         if (done && (*done)[so.req]) {
             for (uint32_t k = so.rank + 1; k <= S.n_req; ++k) rows += hist[S.hist_off + 2 * k];
         } else {
@@ -360,7 +378,7 @@ gace_status finish_compiled(gace_ctx* c, CompiledBatch& cb, const gace_request* 
         rp += rows * so.n_preds;
         if (per_req) per_req[so.req] = GACE_OK;
     }
-    gace_status worst = GACE_OK;
+    gace_status worst = scan_failed ? GACE_EDEVICE : GACE_OK;
     for (const JoinOut& jo : cb.joins) {
         const gace_status s = write_join(c, jo, reqs, !(done && (*done)[jo.req]));
         if (s == GACE_OK) {

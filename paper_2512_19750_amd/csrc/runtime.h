@@ -50,7 +50,7 @@ gace_schedule default_schedule();
 
 // kernel launchers (kernels.hip; internal, not part of the public ABI)
 extern "C" {
-hipError_t gace_launch_init(const void* plan, void* head, void* counts, void* hist, void* accs, void* arena,
+hipError_t gace_launch_init(const void* plan, void* items, void* head, void* counts, void* hist, void* accs, void* arena,
                             hipStream_t stream);
 hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream);
 hipError_t gace_launch_join(const void* args, uint32_t grid, int beside_scan, hipStream_t stream);
