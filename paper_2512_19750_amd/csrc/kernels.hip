@@ -2259,12 +2259,15 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))
 
 // zero the per-batch accumulators (a kernel, not a memset, so it can be
 // captured in a graph and replayed)
-__global__ void __launch_bounds__(kWG) gace_init_kernel(const uint8_t* plan, Item* items, uint32_t* head,
-                                                        unsigned long long* counts, unsigned long long* hist,
-                                                        JoinAcc* accs, Arena* arena) {
-    const PlanHdr H = *(const PlanHdr*)plan;
+__global__ void __launch_bounds__(kWG) gace_init_kernel(uint8_t* plan, const uint8_t* src, uint64_t src_bytes,
+                                                        Item* items, uint32_t* head, unsigned long long* counts,
+                                                        unsigned long long* hist, JoinAcc* accs, Arena* arena) {
+    const PlanHdr H = *(const PlanHdr*)(src_bytes ? src : plan);
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // a small plan comes from the pinned staging buffer (16-byte words)
+    for (uint64_t i = tid; i < src_bytes / 16; i += stride) ((uint4*)plan)[i] = ((const uint4*)src)[i];
+    if (tid < (src_bytes & 15)) plan[src_bytes / 16 * 16 + tid] = src[src_bytes / 16 * 16 + tid];
     for (uint64_t i = tid; i < H.n_counts; i += stride) counts[i] = 0;
     for (uint64_t i = tid; i < H.n_hist; i += stride) hist[i] = 0;
     const uint64_t nacc = (uint64_t)H.n_joins * (sizeof(JoinAcc) / 8);
@@ -2545,11 +2548,11 @@ const void* gace_kernel_handle(int which) {
 }
 
 // launchers used by the host runtime (internal; not part of the public ABI)
-hipError_t gace_launch_init(const void* plan, void* items, void* head, void* counts, void* hist, void* accs,
-                            void* arena, hipStream_t stream) {
+hipError_t gace_launch_init(const void* plan, const void* src, uint64_t src_bytes, void* items, void* head,
+                            void* counts, void* hist, void* accs, void* arena, hipStream_t stream) {
     (void)hipGetLastError();   // report this launch's error, not an earlier call's
-    hipLaunchKernelGGL(gace::gace_init_kernel, dim3(256), dim3(gace::kWG), 0, stream, (const uint8_t*)plan,
-                       (gace::Item*)items, (uint32_t*)head, (unsigned long long*)counts, (unsigned long long*)hist,
+    hipLaunchKernelGGL(gace::gace_init_kernel, dim3(256), dim3(gace::kWG), 0, stream, (uint8_t*)plan,
+                       (const uint8_t*)src, src_bytes, (gace::Item*)items, (uint32_t*)head, (unsigned long long*)counts, (unsigned long long*)hist,
                        (gace::JoinAcc*)accs, (gace::Arena*)arena);
     return hipGetLastError();
 }

@@ -151,7 +151,7 @@ extern "C" gace_status gace_probe_selectivity_noalloc(const gace_table* table, c
     NA_TRY(hipMemcpyAsync(plan, cb.plan.data(), plan_b, hipMemcpyHostToDevice, st), "plan upload");
     if (items_b) NA_TRY(hipMemcpyAsync(items, cb.items.data(), items_b, hipMemcpyHostToDevice, st), "item upload");
     // the init kernel zeroes the counters, the histogram and the queue heads
-    NA_TRY(gace_launch_init(plan, items, head, cnt, hist, misc + 512, arena, st), "init kernel");
+    NA_TRY(gace_launch_init(plan, nullptr, 0, items, head, cnt, hist, misc + 512, arena, st), "init kernel");
     BatchArgsHost a;
     std::memset(&a, 0, sizeof(a));
     a.plan = plan;

@@ -74,6 +74,7 @@ struct PlanHdr {
 // entry is written).  Workgroups that find the item queue empty run the
 // list, so a probe's kept tiles spread one per workgroup instead of queueing
 // behind each other inside one item.
+constexpr uint64_t kInitCopyMax = 64ull << 10;        // plans up to this size are copied by the init kernel
 constexpr uint32_t kSpillMax = 16384;                  // spill-list entries per batch, at most
 constexpr uint32_t kSpillChunkKept = 8;                // spill when at most this many kept blocks per 64 expected
 constexpr uint64_t kSpillPolls = 1ull << 26;           // a drain wait gives up after this many polls

@@ -166,7 +166,8 @@ static gace_status run_branch(gace_ctx* c, int k, hipStream_t s, bool use_graph)
 // are left out: a single selectivity probe is init + scan on one stream.
 static gace_status launch_batch(gace_ctx* c, hipStream_t st, hipStream_t side, bool scans, bool joins, bool beside,
                                 bool scan_one_per_cu, bool use_graph) {
-    HIP_TRY(gace_launch_init(c->d_plan, c->d_items, c->d_head, c->d_counts, c->d_hist, c->d_accs, c->d_arena, st),
+    HIP_TRY(gace_launch_init(c->d_plan, c->d_stage, c->stage_copy, c->d_items, c->d_head, c->d_counts, c->d_hist,
+                             c->d_accs, c->d_arena, st),
             "init kernel");
     if (joins) {
         HIP_TRY(hipEventRecord(c->ev_fork, st), "fork event");
@@ -225,10 +226,15 @@ gace_status launch_compiled(gace_ctx* c, CompiledBatch& cb, hipStream_t st, bool
     if (items_in_plan) {
         hs->items_off = items_b ? (uint32_t)items_at : 0u;
         std::memcpy(c->h_stage + items_at, cb.items.data(), items_b);
-        HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, items_b ? items_at + items_b : plan_b, hipMemcpyHostToDevice,
-                               st), "plan upload");
+        const uint64_t up = items_b ? items_at + items_b : plan_b;
+        // a small plan is copied by the init kernel, which reads the pinned
+        // staging buffer: one GPU operation fewer per call
+        c->stage_copy = c->d_stage && up <= kInitCopyMax ? up : 0;
+        if (!c->stage_copy)
+            HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, up, hipMemcpyHostToDevice, st), "plan upload");
     } else {
         hs->items_off = 0;
+        c->stage_copy = 0;
         std::memcpy(c->h_stage + kPlanCap, cb.items.data(), items_b);
         HIP_TRY(hipMemcpyAsync(c->d_plan, c->h_stage, plan_b, hipMemcpyHostToDevice, st), "plan upload");
         HIP_TRY(hipMemcpyAsync(c->d_items, c->h_stage + kPlanCap, items_b, hipMemcpyHostToDevice, st), "item upload");
@@ -540,6 +546,8 @@ gace_status gace_create(int hip_device, uint64_t workspace_bytes, gace_ctx** out
         std::memset(c->h_flags, 0, kMaxFlags * sizeof(uint32_t));
         void* dr = nullptr;
         void* df = nullptr;
+        void* ds = nullptr;
+        if (hipHostGetDevicePointer(&ds, c->h_stage, 0) == hipSuccess) c->d_stage = (const uint8_t*)ds;
         if (hipHostGetDevicePointer(&dr, c->h_result, 0) == hipSuccess &&
             hipHostGetDevicePointer(&df, c->h_flags, 0) == hipSuccess) {
             c->d_host_res = (uint8_t*)dr;

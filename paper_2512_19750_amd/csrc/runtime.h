@@ -50,7 +50,8 @@ gace_schedule default_schedule();
 
 // kernel launchers (kernels.hip; internal, not part of the public ABI)
 extern "C" {
-hipError_t gace_launch_init(const void* plan, void* items, void* head, void* counts, void* hist, void* accs, void* arena,
+hipError_t gace_launch_init(const void* plan, const void* src, uint64_t src_bytes, void* items, void* head, void* counts,
+                            void* hist, void* accs, void* arena,
                             hipStream_t stream);
 hipError_t gace_launch_scan(const void* args, uint32_t grid, hipStream_t stream);
 hipError_t gace_launch_join(const void* args, uint32_t grid, int beside_scan, hipStream_t stream);
@@ -84,6 +85,8 @@ struct gace_ctx {
     uint64_t arena_bytes = 0;
     // pinned host staging
     uint8_t* h_stage = nullptr;     // plan + items upload
+    const uint8_t* d_stage = nullptr;   // device address of h_stage (small plans: the init kernel copies them)
+    uint64_t stage_copy = 0;        // bytes of h_stage the next init kernel copies to the plan region
     uint8_t* h_result = nullptr;    // counts + hist + accs download
     // per-request completion: kernels write finished scans' and joins'
     // results into h_result and raise their flags (device addresses of both)
