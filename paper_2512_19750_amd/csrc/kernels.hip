@@ -5,13 +5,17 @@
 //   SCAN     kept blocks of one table, all predicates of the requests sharing
 //            the scan (selectivity probe, Sec. III-B; Exp. D "Key-Only +
 //            Bitmask": only referenced columns are read, per-row predicate
-//            bits are reduced in registers and never stored)
+//            bits are reduced in registers and never stored); in a small
+//            batch, a sparse scan's item keeps its chunk's first kept block
+//            and spills the others to a list that idle workgroups run
 //   JHEAVY   a join's heavy-hitter table, from a small sample of its keys
 //   JHIST    per-item hash-partition counts of the sampled join keys (heavy
 //            keys counted per table slot instead)
 //   JOFF     per-item offsets inside each partition
 //   JBASE    partition starts; the partition buffer is carved from the arena
 //   JSCATTER sampled keys other than heavy ones -> their hash partitions
+//            (or first-pass buckets when the fan-out needs two passes)
+//   JSCATTER2 each first-pass bucket of a group of items -> its partitions
 //   JAGG     each partition aggregated in an LDS key table -> f_R(k), f_S(k)
 //            -> NDV (Eq. 1) and sum f_R f_S (key-only aggregation, Sec. III-B)
 // Items of a join wait on the previous phase's completion counter; the host
@@ -2182,7 +2186,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3, 8))
 
 // join phases (queue 1: items [n_scan_items, n_items), in phase order).
 // KP staged keys per thread in the partitioning tiles: kPerBig when the join
-// kernel has the GPU to itself; kPerSmall (143 instead of 226 VGPRs) when a
+// kernel has the GPU to itself; kPerSmall (160 instead of 240 VGPRs) when a
 // scan kernel runs beside it, so a CU that holds a scan workgroup still fits
 // two join waves per SIMD.
 template <int KP>
